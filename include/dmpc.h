@@ -1,0 +1,168 @@
+/*
+ * dmpc.h -- C ABI of the batched differentiable MPC layer on MI355X (gfx950).
+ *
+ * The layer solves, for every instance b of a batch, the box-constrained
+ * optimal control problem of CA-AC-MPC eq. (3):
+ *
+ *     min_{x,u}  sum_{t=0}^{T_b-1} 1/2 z_t^T C_t z_t + c_t^T z_t,   z_t = (x_t, u_t)
+ *     s.t.       x_{t+1} = f(x_t, u_t),  x_0 = x_init,  u_lo <= u_t <= u_hi
+ *
+ * by control-limited iLQR (Sec. IV: rollout and linearisation, Riccati backward
+ * pass with input bounds, forward pass with a four-point line search; Alg. 2,
+ * inner loop), and returns the gradient of an external loss w.r.t. (C_t, c_t,
+ * x_init) by implicit differentiation of the KKT conditions at the returned
+ * solution (Sec. IV, after eq. (3)).
+ *
+ * Dynamics f: one RK4 step of a 13-state quadrotor (p[3], q[4] scalar-first,
+ * v[3], w[3]) driven by four rotor thrusts in an X configuration (rotor i at
+ * angle pi/4 + i pi/2, spin signs +,-,+,-); A_t, B_t are the exact derivatives
+ * of that discrete map.  There is no terminal cost, so x_T is not formed.
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers owned by the caller; the library
+ *    never allocates or frees device memory on these paths.  Scratch space is
+ *    the caller's workspace (see dmpc_workspace_bytes).
+ *  - Layout is instance-major, row-major, float32 unless stated:
+ *      x0        [B][13]
+ *      Q         [B][T_max][17]   cost_kind DMPC_COST_DIAG: diagonal of C_t
+ *                [B][T_max][153]  cost_kind DMPC_COST_DENSE: upper triangle of
+ *                                 C_t, packed row by row: (0,0),(0,1)..(0,16),(1,1)..
+ *      p         [B][T_max][17]   c_t
+ *      u_lo/u_hi [B][4]
+ *      T         [B] int32 horizons in [0, T_max], or NULL (every T_b = T_max)
+ *      u_out     [B][T_max][4],  x_out [B][T_max][13]; stages t >= T_b are zero
+ *  - Calls are asynchronous on `stream` (a hipStream_t passed as void*), never
+ *    synchronise the host and never allocate, so a caller may capture them in a
+ *    HIP graph.  A handle is bound to one device and is not thread-safe.
+ *  - Return value: DMPC_OK or a negative DMPC_E* code; dmpc_last_error() gives
+ *    the message.  Numerical trouble is never an error return: it is reported
+ *    per instance in `status`.
+ */
+#ifndef DMPC_H
+#define DMPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DMPC_NX 13
+#define DMPC_NU 4
+#define DMPC_NZ 17
+#define DMPC_NPACK 153
+#define DMPC_T_LIMIT 1024 /* largest supported T_max */
+#define DMPC_K_LIMIT 255  /* largest supported max_iter (fits the 8-bit count) */
+
+/* return codes */
+#define DMPC_OK 0
+#define DMPC_EINVAL (-1)      /* bad sizes, NULL required pointer, lo > hi on the host side */
+#define DMPC_EUNSUPPORTED (-2) /* T_max > DMPC_T_LIMIT, unknown cost kind, checkpointing not built */
+#define DMPC_EHIP (-3)        /* HIP runtime or launch error */
+#define DMPC_EWORKSPACE (-4)  /* workspace NULL or smaller than dmpc_workspace_bytes() */
+
+/* cost kinds */
+#define DMPC_COST_DIAG 0
+#define DMPC_COST_DENSE 1
+
+/* config flags */
+#define DMPC_NEED_GRAD 0x1u /* forward also factors the stages at (x*, u*) for dmpc_backward */
+#define DMPC_PLAIN 0x2u     /* per-launch form: init, three launches per iteration, tail, outputs */
+#define DMPC_LPT 0x4u       /* persistent form: process instances by decreasing T_b */
+
+/* per-instance status word */
+#define DMPC_ST_CONVERGED 0x1u   /* tol_du > 0 and ||U^k - U^{k-1}||_inf < tol_du was reached */
+#define DMPC_ST_MAXITER 0x2u     /* tol_du > 0 and the iteration cap was hit first */
+#define DMPC_ST_NONFINITE 0x4u   /* a non-finite value appeared (all line-search costs non-finite) */
+#define DMPC_ST_FP64 0x8u        /* a stage Cholesky pivot fell below fp64_pivot; redone in FP64 */
+#define DMPC_ST_QPMAXITER 0x10u  /* a stagewise box-QP hit its iteration cap */
+#define DMPC_ST_REGULARIZED 0x20u /* a non-positive pivot remained; the block was shifted */
+#define DMPC_ST_ITERS_SHIFT 8    /* bits 8..15: iLQR iterations performed */
+
+/* decision log (optional forward output): [B][max_iter][1 + T_max] bytes.
+ * Byte 0 of iteration k: index of the chosen line-search candidate
+ * (0..3 for alpha = 1, 0.5, 0.25, 0.1; 255 when every candidate was
+ * non-finite).  Byte 1 + t: box-QP pattern of stage t, control i in bits
+ * 2i..2i+1 (0 free, 1 at the lower bound, 2 at the upper bound).  Iterations
+ * not performed are left as written by the caller. */
+#define DMPC_ALPHA_NONE 255
+
+typedef struct {
+  float mass;  /* kg */
+  float Jxx, Jyy, Jzz; /* principal inertia, kg m^2 */
+  float arm;   /* rotor distance from the centre, m */
+  float kappa; /* yaw torque per unit thrust, m */
+  float dt;    /* RK4 step, s */
+  float g;     /* gravity, m/s^2 */
+} dmpc_quad_params;
+
+typedef struct {
+  int32_t B;          /* batch size (>= 0) */
+  int32_t T_max;      /* stage dimension of every [B][T_max][...] array (>= 1) */
+  int32_t cost_kind;  /* DMPC_COST_DIAG or DMPC_COST_DENSE */
+  int32_t max_iter;   /* iLQR iterations K (0..DMPC_K_LIMIT) */
+  float tol_du;       /* <= 0: always K iterations; > 0: per-instance stop at ||dU||_inf < tol_du */
+  int32_t ckpt_every; /* 0: store every stage's factors for the backward; > 0: reserved (EUNSUPPORTED) */
+  float fp64_pivot;   /* Cholesky pivots below this are redone in FP64; <= 0 disables */
+  uint32_t flags;     /* DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT */
+} dmpc_config;
+
+typedef struct dmpc_handle_s* dmpc_handle;
+
+/* Create a handle on HIP device `device` (queries its compute-unit count).
+ * Returns DMPC_EHIP when no such device is present. */
+int dmpc_create(dmpc_handle* h, int device);
+int dmpc_destroy(dmpc_handle h);
+
+/* Host-only check of a configuration; needs no GPU.  DMPC_OK, DMPC_EINVAL or
+ * DMPC_EUNSUPPORTED. */
+int dmpc_validate(const dmpc_config* cfg);
+
+/* Bytes of device workspace a forward/backward pair needs for cfg (0 if cfg
+ * is invalid).  Host-only. */
+size_t dmpc_workspace_bytes(const dmpc_config* cfg);
+
+/* Forward solve (Alg. 2 inner loop).  Reads x0, Q, p, u_lo, u_hi, T; writes
+ * u_out, x_out (may be NULL), status [B] (bits above, iterations in bits
+ * 8..15) and, when decision_log is not NULL, the decisions taken.  The
+ * workspace (>= dmpc_workspace_bytes(cfg) bytes, 256-byte aligned) keeps the
+ * solution and, with DMPC_NEED_GRAD, the stage factors read by dmpc_backward;
+ * it must not be reused before that backward has run. */
+int dmpc_forward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* x0, const float* Q,
+                 const float* p, const float* u_lo, const float* u_hi, const int32_t* T, float* u_out,
+                 float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes, uint8_t* decision_log,
+                 void* stream);
+
+/* Backward (Sec. IV after eq. (3)): given dL/du* [B][T_max][4] and
+ * optionally dL/dx* [B][T_max][13] (NULL = zero), writes
+ * grad_Q [B][T_max][17|153] (layout of Q; for the packed dense cost the
+ * derivative w.r.t. each packed entry, i.e. G_ij + G_ji off the diagonal),
+ * grad_p [B][T_max][17] and grad_x0 [B][13].  Uses the workspace of the
+ * preceding dmpc_forward, which must have had DMPC_NEED_GRAD and the same cfg.
+ * The active set is the one of the forward solution (controls equal to a
+ * bound are held fixed). */
+int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, const void* workspace, size_t workspace_bytes,
+                  const float* grad_u, const float* grad_x, float* grad_Q, float* grad_p, float* grad_x0,
+                  void* stream);
+
+/* Number of kernel launches the last dmpc_forward / dmpc_backward issued on
+ * this handle (host-side count; for tests of the launch structure). */
+int dmpc_last_launch_count(dmpc_handle h);
+
+/* Graph helpers: begin capturing `stream`; enqueue dmpc_forward/dmpc_backward
+ * calls; end the capture into an executable graph.  The captured work uses
+ * kernels only (no memset or copy nodes). */
+int dmpc_capture_begin(dmpc_handle h, void* stream);
+int dmpc_capture_end(dmpc_handle h, void* stream, void** graph_exec);
+int dmpc_graph_launch(dmpc_handle h, void* graph_exec, void* stream);
+int dmpc_graph_destroy(dmpc_handle h, void* graph_exec);
+
+/* Message for the last error on this handle (or of the last failed call
+ * without a handle when h is NULL). */
+const char* dmpc_last_error(dmpc_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,230 @@
+"""Batched differentiable MPC layer (CA-AC-MPC's CA-DiffMPC) on MI355X.
+
+Thin ctypes binding over the C ABI in include/dmpc.h (libdmpc.so, built for
+gfx950 by paper_2605_29155_amd/build.py).  This module only marshals
+arguments: every step of the forward solve and of the backward runs in the
+HIP kernels.  There is no CPU fallback: without the built library every call
+raises.
+
+PyTorch provides device memory and the stream; tensors are float32 on the GPU,
+instance-major: x0 [B,13], Q [B,T,17] (diagonal) or [B,T,153] (packed upper
+triangle), p [B,T,17], u_lo/u_hi [B,4], T [B] int32 or None.
+"""
+import ctypes as C
+import os
+
+from . import build as _build
+
+NX, NU, NZ, NPACK = 13, 4, 17, 153
+COST_DIAG, COST_DENSE = 0, 1
+NEED_GRAD, PLAIN, LPT = 0x1, 0x2, 0x4
+ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_FP64, ST_QPMAXITER, ST_REGULARIZED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+ITERS_SHIFT = 8
+ALPHA_NONE = 255
+ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "EHIP", -4: "EWORKSPACE"}
+
+
+class QuadParams(C.Structure):
+    _fields_ = [(n, C.c_float) for n in ("mass", "Jxx", "Jyy", "Jzz", "arm", "kappa", "dt", "g")]
+
+
+class Config(C.Structure):
+    _fields_ = [("B", C.c_int32), ("T_max", C.c_int32), ("cost_kind", C.c_int32), ("max_iter", C.c_int32),
+                ("tol_du", C.c_float), ("ckpt_every", C.c_int32), ("fp64_pivot", C.c_float),
+                ("flags", C.c_uint32)]
+
+
+class DMPCError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            raise DMPCError("libdmpc.so is not built (run paper_2605_29155_amd/build.py); "
+                            "there is no fallback path")
+        L = C.CDLL(_build.LIB)
+        vp, sz, i32 = C.c_void_p, C.c_size_t, C.c_int
+        L.dmpc_create.argtypes = [C.POINTER(vp), i32]
+        L.dmpc_destroy.argtypes = [vp]
+        L.dmpc_validate.argtypes = [C.POINTER(Config)]
+        L.dmpc_workspace_bytes.argtypes = [C.POINTER(Config)]
+        L.dmpc_workspace_bytes.restype = sz
+        L.dmpc_forward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 10 + [vp, sz, vp, vp]
+        L.dmpc_backward.argtypes = [vp, C.POINTER(Config), vp, sz] + [vp] * 5 + [vp]
+        L.dmpc_last_launch_count.argtypes = [vp]
+        L.dmpc_capture_begin.argtypes = [vp, vp]
+        L.dmpc_capture_end.argtypes = [vp, vp, C.POINTER(vp)]
+        L.dmpc_graph_launch.argtypes = [vp, vp, vp]
+        L.dmpc_graph_destroy.argtypes = [vp, vp]
+        L.dmpc_last_error.argtypes = [vp]
+        L.dmpc_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def quad_params(d):
+    return QuadParams(*[float(d[k]) for k in ("mass", "Jxx", "Jyy", "Jzz", "arm", "kappa", "dt", "g")])
+
+
+def make_config(B, T_max, cost_kind=COST_DIAG, max_iter=5, tol_du=0.0, flags=0, fp64_pivot=1e-6, ckpt_every=0):
+    return Config(int(B), int(T_max), int(cost_kind), int(max_iter), float(tol_du), int(ckpt_every),
+                  float(fp64_pivot), int(flags))
+
+
+def validate(cfg):
+    return lib().dmpc_validate(C.byref(cfg))
+
+
+def workspace_bytes(cfg):
+    return int(lib().dmpc_workspace_bytes(C.byref(cfg)))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Handle:
+    """One dmpc handle per device."""
+
+    def __init__(self, device=0):
+        self._h = C.c_void_p()
+        rc = lib().dmpc_create(C.byref(self._h), int(device))
+        if rc != 0:
+            raise DMPCError("dmpc_create: %s" % lib().dmpc_last_error(None).decode())
+        self.device = device
+
+    def check(self, rc, what):
+        if rc != 0:
+            raise DMPCError("%s: %s (%s)" % (what, ERRORS.get(rc, rc), lib().dmpc_last_error(self._h).decode()))
+
+    def launch_count(self):
+        return lib().dmpc_last_launch_count(self._h)
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().dmpc_destroy(self._h)
+        except Exception:
+            pass
+
+
+def alloc_workspace(cfg, device):
+    """Device workspace of dmpc_workspace_bytes(cfg), 256-byte aligned."""
+    import torch
+    n = workspace_bytes(cfg)
+    if n == 0:
+        raise DMPCError("invalid configuration")
+    buf = torch.empty(n + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + n]
+
+
+def forward_raw(h, cfg, params, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, ws, dlog=None, stream=None):
+    rc = lib().dmpc_forward(h._h, C.byref(cfg), params, _ptr(x0), _ptr(Q), _ptr(p), _ptr(u_lo), _ptr(u_hi), _ptr(T),
+                            _ptr(u_out), _ptr(x_out), _ptr(status), _ptr(ws), ws.numel() if ws is not None else 0,
+                            _ptr(dlog), _stream(stream))
+    h.check(rc, "dmpc_forward")
+
+
+def backward_raw(h, cfg, ws, grad_u, grad_x, grad_Q, grad_p, grad_x0, stream=None):
+    rc = lib().dmpc_backward(h._h, C.byref(cfg), _ptr(ws), ws.numel(), _ptr(grad_u), _ptr(grad_x), _ptr(grad_Q),
+                             _ptr(grad_p), _ptr(grad_x0), _stream(stream))
+    h.check(rc, "dmpc_backward")
+
+
+def capture_begin(h, stream=None):
+    h.check(lib().dmpc_capture_begin(h._h, _stream(stream)), "dmpc_capture_begin")
+
+
+def capture_end(h, stream=None):
+    g = C.c_void_p()
+    h.check(lib().dmpc_capture_end(h._h, _stream(stream), C.byref(g)), "dmpc_capture_end")
+    return g
+
+
+def graph_launch(h, g, stream=None):
+    h.check(lib().dmpc_graph_launch(h._h, g, _stream(stream)), "dmpc_graph_launch")
+
+
+def graph_destroy(h, g):
+    h.check(lib().dmpc_graph_destroy(h._h, g), "dmpc_graph_destroy")
+
+
+def _make_function():
+    import torch
+
+    class DMPCFunction(torch.autograd.Function):
+        """u*, x*, status = DMPCFunction.apply(x0, Q, p, u_lo, u_hi, T, layer).
+
+        Differentiable in x0, Q and p (Sec. IV after eq. (3)); the backward
+        reuses the stage factors the forward stored in its workspace."""
+
+        @staticmethod
+        def forward(ctx, x0, Q, p, u_lo, u_hi, T, layer):
+            B, Tm = p.shape[0], p.shape[1]
+            need = any(ctx.needs_input_grad[:3])
+            cfg = layer.config(B, Tm, need_grad=need)
+            ws = alloc_workspace(cfg, p.device)
+            u = torch.empty(B, Tm, NU, device=p.device, dtype=torch.float32)
+            x = torch.empty(B, Tm, NX, device=p.device, dtype=torch.float32)
+            st = torch.empty(B, device=p.device, dtype=torch.int32)
+            forward_raw(layer.handle, cfg, layer.params, x0, Q, p, u_lo, u_hi, T, u, x, st, ws)
+            ctx.cfg, ctx.ws, ctx.layer = cfg, ws, layer
+            ctx.shapes = (x0.shape, Q.shape, p.shape)
+            ctx.mark_non_differentiable(st)
+            return u, x, st
+
+        @staticmethod
+        def backward(ctx, gu, gx, _gst):
+            sx0, sQ, sp = ctx.shapes
+            dev = ctx.ws.device
+            gu = torch.zeros(sp[0], sp[1], NU, device=dev) if gu is None else gu.contiguous().float()
+            gx = None if gx is None else gx.contiguous().float()
+            gQ = torch.empty(sQ, device=dev, dtype=torch.float32)
+            gp = torch.empty(sp, device=dev, dtype=torch.float32)
+            gx0 = torch.empty(sx0, device=dev, dtype=torch.float32)
+            backward_raw(ctx.layer.handle, ctx.cfg, ctx.ws, gu, gx, gQ, gp, gx0)
+            return gx0, gQ, gp, None, None, None, None
+
+    return DMPCFunction
+
+
+_function = None
+
+
+def DMPCFunction():
+    """The module-level autograd.Function (defined once)."""
+    global _function
+    if _function is None:
+        _function = _make_function()
+    return _function
+
+
+class DMPCLayer:
+    """Callable layer: (x0, Q, p, u_lo, u_hi, T=None) -> (u*, x*, status)."""
+
+    def __init__(self, params, max_iter=5, tol_du=0.0, cost_kind=COST_DIAG, plain=False, lpt=True,
+                 fp64_pivot=1e-6, device=0):
+        self.handle = Handle(device)
+        self.params = quad_params(params) if isinstance(params, dict) else params
+        self.max_iter, self.tol_du, self.cost_kind = max_iter, tol_du, cost_kind
+        self.plain, self.lpt, self.fp64_pivot = plain, lpt, fp64_pivot
+
+    def config(self, B, T_max, need_grad=True):
+        flags = (NEED_GRAD if need_grad else 0) | (PLAIN if self.plain else 0) | (LPT if self.lpt else 0)
+        return make_config(B, T_max, self.cost_kind, self.max_iter, self.tol_du, flags, self.fp64_pivot)
+
+    def __call__(self, x0, Q, p, u_lo, u_hi, T=None):
+        return DMPCFunction().apply(x0, Q, p, u_lo, u_hi, T, self)

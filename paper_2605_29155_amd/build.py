@@ -1,0 +1,30 @@
+"""Build the HIP library libdmpc.so for gfx950 (in-tree, next to this file)."""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libdmpc.so")
+SRC = os.path.join(HERE, "csrc", "dmpc.hip")
+DEPS = [SRC, os.path.join(HERE, "csrc", "dmpc_device.hpp"), os.path.join(ROOT, "include", "dmpc.h")]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+         # packed FP32 VALU ops stay disabled: they are not used by this library
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-I" + os.path.join(ROOT, "include")]
+
+
+def build(force: bool = True) -> str:
+    if not force and os.path.exists(LIB):
+        if os.path.getmtime(LIB) >= max(os.path.getmtime(p) for p in DEPS):
+            return LIB
+    tmp = LIB + ".tmp"
+    subprocess.run([HIPCC] + FLAGS + [SRC, "-o", tmp], check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(force="--if-stale" not in sys.argv))

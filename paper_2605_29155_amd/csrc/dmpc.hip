@@ -1,0 +1,1069 @@
+// dmpc.hip -- kernels and C ABI of the batched differentiable MPC layer
+// (CA-AC-MPC, Sec. IV: control-limited iLQR forward with rollout and
+// linearisation, Riccati backward pass with input bounds, line-search forward
+// pass; implicit-KKT backward).  Target: gfx950 only.
+//
+// Two launch forms share the same device routines:
+//  * persistent form: one launch runs the whole forward for every instance
+//    (waves pop four-instance units from an atomic queue; per-instance early
+//    exit; optional longest-horizon-first order), one launch runs the backward;
+//  * per-launch form (DMPC_PLAIN): init, then linearise / Riccati / line search
+//    as three launches per iteration, then the tail and the outputs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "dmpc.h"
+#include "dmpc_device.hpp"
+
+using namespace dmpc_dev;
+
+namespace {
+
+struct Ws {
+  int* state;   // [B][SW]
+  int* queue;   // work counter of the persistent launch
+  int* order;   // [B] instance order (longest horizon first)
+  float* traj;  // [B][NSLOT][Tm][ZS]
+  float* gains; // [B][Tm][GS]
+  float* lin;   // [B][Tm][FS]  (per-launch form)
+  float* tail;  // [B][Tm][TS]  (stage factors for the backward)
+  float* ktil;  // [B][Tm][4]   (backward scratch)
+};
+
+struct KArgs {
+  Dyn P;
+  int B, Tm, K, need_grad, use_order, nquads;
+  float tol, piv;
+  const float *x0, *Q, *p, *lo, *hi;
+  const int* T;
+  float *u_out, *x_out;
+  uint32_t* status;
+  uint8_t* dlog;
+  Ws ws;
+  const float *gu, *gx;
+  float *gQ, *gp, *gx0;
+};
+
+struct Grp {
+  int b, T, l, col;
+  bool valid;
+  float lo[4], hi[4];
+};
+
+__device__ __forceinline__ void mem_fence_wg() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ float* traj_at(const KArgs& A, int b, int s, int t) {
+  return A.ws.traj + (((size_t)b * NSLOT + s) * A.Tm + t) * ZS;
+}
+__device__ __forceinline__ float* gains_at(const KArgs& A, int b, int t) {
+  return A.ws.gains + ((size_t)b * A.Tm + t) * GS;
+}
+__device__ __forceinline__ float* lin_at(const KArgs& A, int b, int t) { return A.ws.lin + ((size_t)b * A.Tm + t) * FS; }
+__device__ __forceinline__ float* tail_at(const KArgs& A, int b, int t) {
+  return A.ws.tail + ((size_t)b * A.Tm + t) * TS;
+}
+
+__device__ __forceinline__ int pidx(int i, int j) { return 17 * i - (i * (i - 1)) / 2 + (j - i); }
+
+__device__ __forceinline__ void load_z(const float* zp, float* z) {
+  const float4 a = *(const float4*)(zp);
+  const float4 b = *(const float4*)(zp + 4);
+  const float4 c = *(const float4*)(zp + 8);
+  const float4 u = *(const float4*)(zp + 16);
+  z[0] = a.x; z[1] = a.y; z[2] = a.z; z[3] = a.w;
+  z[4] = b.x; z[5] = b.y; z[6] = b.z; z[7] = b.w;
+  z[8] = c.x; z[9] = c.y; z[10] = c.z; z[11] = c.w;
+  z[12] = zp[12];
+  z[13] = u.x; z[14] = u.y; z[15] = u.z; z[16] = u.w;
+}
+
+__device__ __forceinline__ void store_z(float* zp, const float* x, const float* u) {
+  *(float4*)(zp) = make_float4(x[0], x[1], x[2], x[3]);
+  *(float4*)(zp + 4) = make_float4(x[4], x[5], x[6], x[7]);
+  *(float4*)(zp + 8) = make_float4(x[8], x[9], x[10], x[11]);
+  *(float4*)(zp + 12) = make_float4(x[12], 0.f, 0.f, 0.f);
+  *(float4*)(zp + 16) = make_float4(u[0], u[1], u[2], u[3]);
+}
+
+__device__ __forceinline__ Grp make_grp(const KArgs& A, int slot, int l) {
+  Grp G;
+  G.l = l;
+  G.col = (l == 0) ? 16 : l;
+  G.valid = slot < A.B;
+  G.b = G.valid ? (A.use_order ? A.ws.order[slot] : slot) : 0;
+  int T = A.Tm;
+  if (G.valid && A.T) T = A.T[G.b];
+  T = T < 0 ? 0 : (T > A.Tm ? A.Tm : T);
+  G.T = G.valid ? T : 0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    G.lo[a] = G.valid ? A.lo[(size_t)G.b * 4 + a] : 0.f;
+    G.hi[a] = G.valid ? A.hi[(size_t)G.b * 4 + a] : 0.f;
+  }
+  return G;
+}
+
+// initial nominal (Alg. 2, Rollout): U^0 = clamp(m g / 4), X^0 by RK4
+__device__ void grp_init(const KArgs& A, const Grp& G) {
+  float x[NX], xn[NX], u[NU];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) x[i] = A.x0[(size_t)G.b * NX + i];
+#pragma unroll
+  for (int a = 0; a < NU; ++a) u[a] = clampf(A.P.hover, G.lo[a], G.hi[a]);
+  for (int t = 0; t < G.T; ++t) {
+    if (G.l == 0) store_z(traj_at(A, G.b, 0, t), x, u);
+    if (t + 1 < G.T) {
+      rk4(A.P, x, u, xn);
+#pragma unroll
+      for (int i = 0; i < NX; ++i) x[i] = xn[i];
+    }
+  }
+}
+
+// One backward sweep t = T-1 .. 0 of the Riccati recursion (Sec. IV "Backward
+// pass with input bounds").  MODE 0: stagewise box-QP, writes K_t, k_t to the
+// gains and the pattern to the decision log.  MODE 1 (tail): the active set is
+// fixed to the controls that sit on a bound, writes F_t, K_t and the masked
+// inverse of the free block for the backward.  LIN_INLINE: A_t, B_t computed
+// here (persistent form) or read from the linearisation buffer (per-launch).
+template <bool DENSE, int MODE, bool LIN_INLINE>
+__device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, const LaneDir& D, uint32_t& st) {
+  const int l = G.l, col = G.col, b = G.b, T = G.T;
+  float Vr[NX], vrep[NX];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) {
+    Vr[i] = 0.f;
+    vrep[i] = 0.f;
+  }
+  for (int t = T - 1; t >= 0; --t) {
+    const float* zp = traj_at(A, b, n, t);
+    float zb[NZ];
+    load_z(zp, zb);
+    const bool has_dyn = (t + 1 < T);
+    float Fc[NX];
+    if (has_dyn) {
+      if (LIN_INLINE) {
+        rk4_column(A.P, zb, zb + NX, D, Fc);
+      } else {
+        const float* fp = lin_at(A, b, t) + col * 16;
+#pragma unroll
+        for (int k = 0; k < NX; ++k) Fc[k] = fp[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < NX; ++k) Fc[k] = 0.f;
+    }
+
+    // Y[:, col] = V F[:, col]   (V symmetric: lane k's row k is column k)
+    float Yc[NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) Yc[i] = 0.f;
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      const float f = Fc[k];
+#pragma unroll
+      for (int i = 0; i < NX; ++i) Yc[i] = fmaf(rb(Vr[i], k), f, Yc[i]);
+    }
+    // Q[:, col] = (F^T V F)[:, col]; F[:, 0] = e_0
+    float Qc[NZ];
+    Qc[0] = Yc[0];
+#pragma unroll
+    for (int i = 1; i < NZ; ++i) {
+      float s = 0.f;
+#pragma unroll
+      for (int k = 0; k < NX; ++k) s = fmaf(rb(Fc[k], lane_of(i)), Yc[k], s);
+      Qc[i] = s;
+    }
+    // row 0 of F^T V F, gathered (only lane 0 uses it: its own column is 16)
+    float R0[NZ];
+    R0[0] = Vr[0];
+#pragma unroll
+    for (int j = 1; j < NZ; ++j) R0[j] = rb(Yc[0], lane_of(j));
+
+    // stage cost: Q += C_t, q = g + F^T v with g = C_t z + c_t
+    float qc, q0, Hd[4] = {0.f, 0.f, 0.f, 0.f};
+    {
+      const size_t srow = (size_t)b * A.Tm + t;
+      const float* prow = A.p + srow * NZ;
+      const float zb_c = zp[col < NX ? col : col + 3];
+      if (!DENSE) {
+        const float* qrow = A.Q + srow * NZ;
+        const float qd_c = qrow[col], qd_0 = qrow[0];
+        qc = fmaf(qd_c, zb_c, prow[col]);
+        q0 = fmaf(qd_0, zb[0], prow[0]);
+#pragma unroll
+        for (int i = 1; i < NX; ++i) Qc[i] += (i == col) ? qd_c : 0.f;
+        R0[0] += qd_0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) Hd[a] = qrow[NX + a];
+      } else {
+        const float* crow = A.Q + srow * NPK;
+        float gc = prow[col], g0 = prow[0];
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) {
+          const float cc = crow[i <= col ? pidx(i, col) : pidx(col, i)];
+          const float c0 = crow[i];
+          Qc[i] += cc;
+          R0[i] += c0;
+          gc = fmaf(cc, zb[i], gc);
+          g0 = fmaf(c0, zb[i], g0);
+        }
+        qc = gc;
+        q0 = g0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NX; ++k) qc = fmaf(Fc[k], vrep[k], qc);
+    q0 += vrep[0];
+
+    // replicate the control block: H = Q_uu (upper triangle from column b), q_u
+    float H[16], qu[4];
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+#pragma unroll
+      for (int a = 0; a <= bb; ++a) {
+        const float v = rb(Qc[NX + a], lane_of(NX + bb));
+        H[a * 4 + bb] = v;
+        H[bb * 4 + a] = v;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      H[a * 5] += Hd[a];
+      qu[a] = rb(qc, lane_of(NX + a));
+    }
+    float dl[4], dh[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      dl[a] = G.lo[a] - zb[NX + a];
+      dh[a] = G.hi[a] - zb[NX + a];
+    }
+
+    float kv[4] = {0.f, 0.f, 0.f, 0.f}, fr[4];
+    Chol4 C;
+    float* gp = gains_at(A, b, t);
+    if (MODE == 0) {
+      float kw[4] = {0.f, 0.f, 0.f, 0.f};
+      if (kit > 0) {
+        const float4 w = *(const float4*)(gp + 52);
+        kw[0] = w.x; kw[1] = w.y; kw[2] = w.z; kw[3] = w.w;
+      }
+      boxqp(H, qu, dl, dh, kw, A.piv, kv, fr, C, st);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) fr[a] = (zb[NX + a] == G.lo[a] || zb[NX + a] == G.hi[a]) ? 0.f : 1.f;
+      chol4(H, fr, A.piv, C, st);
+    }
+
+    // gain column: K[:, l] = -Qff^{-1} Q_ux[:, l] on the free rows, 0 on clamped rows
+    float Qux[4], Kc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      Qux[a] = (l == 0) ? R0[NX + a] : Qc[NX + a];
+      Kc[a] = fr[a] * Qux[a];
+    }
+    solve4(C, Kc);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) Kc[a] = -Kc[a];
+
+    // V row l = Q_xx[l, :] + Q_ux[:, l]^T K ;  v_l = Q_x[l] + Q_ux[:, l]^T k
+    float Vn[NX];
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      float s = (l == 0) ? R0[j] : Qc[j];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) s = fmaf(Qux[a], rb(Kc[a], j), s);
+      Vn[j] = s;
+    }
+    float vi = (l == 0) ? q0 : qc;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) vi = fmaf(Qux[a], kv[a], vi);
+    const bool xl = l < NX;
+#pragma unroll
+    for (int j = 0; j < NX; ++j) Vr[j] = xl ? Vn[j] : 0.f;
+    vi = xl ? vi : 0.f;
+#pragma unroll
+    for (int j = 0; j < NX; ++j) vrep[j] = rb(vi, j);
+
+    if (MODE == 0) {
+      if (l < NX) *(float4*)(gp + l * 4) = make_float4(Kc[0], Kc[1], Kc[2], Kc[3]);
+      if (l == NX) *(float4*)(gp + 52) = make_float4(kv[0], kv[1], kv[2], kv[3]);
+      if (A.dlog && l == 0) {
+        unsigned code = 0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const unsigned c = (fr[a] != 0.f) ? 0u : (kv[a] <= dl[a] ? 1u : 2u);
+          code |= c << (2 * a);
+        }
+        A.dlog[((size_t)b * A.K + kit) * (1 + A.Tm) + 1 + t] = (uint8_t)code;
+      }
+    } else {
+      float* tp = tail_at(A, b, t);
+      float* fc = tp + col * 16;
+      *(float4*)(fc) = make_float4(Fc[0], Fc[1], Fc[2], Fc[3]);
+      *(float4*)(fc + 4) = make_float4(Fc[4], Fc[5], Fc[6], Fc[7]);
+      *(float4*)(fc + 8) = make_float4(Fc[8], Fc[9], Fc[10], Fc[11]);
+      fc[12] = Fc[12];
+      if (l == NX) {  // column 0 = e_0 (zero at the last stage)
+        const float e = has_dyn ? 1.f : 0.f;
+        *(float4*)(tp) = make_float4(e, 0.f, 0.f, 0.f);
+        *(float4*)(tp + 4) = make_float4(0.f, 0.f, 0.f, 0.f);
+        *(float4*)(tp + 8) = make_float4(0.f, 0.f, 0.f, 0.f);
+        tp[12] = 0.f;
+      }
+      if (l < NX) *(float4*)(tp + FS + l * 4) = make_float4(Kc[0], Kc[1], Kc[2], Kc[3]);
+      // M = masked inverse of the free block (zero rows/columns on clamped controls)
+      float M[16];
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        float e[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) e[a] = (a == bb) ? fr[bb] : 0.f;
+        solve4(C, e);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) M[a * 4 + bb] = fr[a] * e[a];
+      }
+      if (l == NX + 1) {
+        float* mp = tp + FS + 52;
+        *(float4*)(mp) = make_float4(M[0], M[1], M[2], M[3]);
+        *(float4*)(mp + 4) = make_float4(M[4], M[5], M[6], M[7]);
+        *(float4*)(mp + 8) = make_float4(M[8], M[9], M[10], M[11]);
+        *(float4*)(mp + 12) = make_float4(M[12], M[13], M[14], M[15]);
+      }
+    }
+  }
+}
+
+// Forward pass with line search (Sec. IV): candidate a = lane & 3 rolls out
+// u = clamp(u_bar + alpha k + K (x - x_bar), lo, hi) and sums its cost.
+template <bool DENSE>
+__device__ void grp_ls(const KArgs& A, const Grp& G, int n, float& Jout, float& dmax) {
+  const int a = G.l & 3, b = G.b, T = G.T;
+  const float alpha = a == 0 ? 1.f : (a == 1 ? 0.5f : (a == 2 ? 0.25f : 0.1f));
+  const int sc = (n + 1 + a) % NSLOT;
+  float x[NX], xn[NX];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) x[i] = A.x0[(size_t)b * NX + i];
+  float J = 0.f, dm = 0.f;
+  for (int t = 0; t < T; ++t) {
+    float zb[NZ];
+    load_z(traj_at(A, b, n, t), zb);
+    const float* gp = gains_at(A, b, t);
+    float dx[NX];
+#pragma unroll
+    for (int j = 0; j < NX; ++j) dx[j] = x[j] - zb[j];
+    const float4 kk = *(const float4*)(gp + 52);
+    float u[NU] = {zb[13] + alpha * kk.x, zb[14] + alpha * kk.y, zb[15] + alpha * kk.z, zb[16] + alpha * kk.w};
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      const float4 kj = *(const float4*)(gp + j * 4);
+      u[0] = fmaf(kj.x, dx[j], u[0]);
+      u[1] = fmaf(kj.y, dx[j], u[1]);
+      u[2] = fmaf(kj.z, dx[j], u[2]);
+      u[3] = fmaf(kj.w, dx[j], u[3]);
+    }
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      u[c] = clampf(u[c], G.lo[c], G.hi[c]);
+      dm = fmaxf(dm, fabsf(u[c] - zb[NX + c]));
+    }
+    float z[NZ];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) z[i] = x[i];
+#pragma unroll
+    for (int c = 0; c < NU; ++c) z[NX + c] = u[c];
+    const size_t srow = (size_t)b * A.Tm + t;
+    const float* prow = A.p + srow * NZ;
+    if (!DENSE) {
+      const float* qrow = A.Q + srow * NZ;
+#pragma unroll
+      for (int i = 0; i < NZ; ++i) J = fmaf(fmaf(0.5f * qrow[i], z[i], prow[i]), z[i], J);
+    } else {
+      const float* crow = A.Q + srow * NPK;
+      int m = 0;
+#pragma unroll
+      for (int i = 0; i < NZ; ++i) {
+        float s = 0.5f * crow[m++] * z[i];
+#pragma unroll
+        for (int j = i + 1; j < NZ; ++j) s = fmaf(crow[m++], z[j], s);
+        J = fmaf(s + prow[i], z[i], J);
+      }
+    }
+    if (G.l < 4) store_z(traj_at(A, b, sc, t), x, u);
+    if (t + 1 < T) {
+      rk4(A.P, x, u, xn);
+#pragma unroll
+      for (int i = 0; i < NX; ++i) x[i] = xn[i];
+    }
+  }
+  Jout = J;
+  dmax = dm;
+}
+
+__device__ __forceinline__ float finite_or_inf(float v) {
+  return (v == v && fabsf(v) <= 3.402823466e38f) ? v : INFINITY;
+}
+
+// pick the first minimiser of the four candidate costs; returns -1 if none is finite
+__device__ __forceinline__ int ls_select(float J, float dm, float& dsel) {
+  const float c0 = finite_or_inf(rb(J, 0)), c1 = finite_or_inf(rb(J, 1)), c2 = finite_or_inf(rb(J, 2)),
+              c3 = finite_or_inf(rb(J, 3));
+  const float d0 = rb(dm, 0), d1 = rb(dm, 1), d2 = rb(dm, 2), d3 = rb(dm, 3);
+  int best = -1;
+  float bj = INFINITY;
+  dsel = 0.f;
+  if (c0 < bj) { best = 0; bj = c0; dsel = d0; }
+  if (c1 < bj) { best = 1; bj = c1; dsel = d1; }
+  if (c2 < bj) { best = 2; bj = c2; dsel = d2; }
+  if (c3 < bj) { best = 3; bj = c3; dsel = d3; }
+  return best;
+}
+
+// writes u_out / x_out (zeros past T_b) from the nominal slot
+__device__ void grp_outputs(const KArgs& A, const Grp& G, int n) {
+  const int b = G.b;
+  for (int t = 0; t < A.Tm; ++t) {
+    const float* zp = traj_at(A, b, n, t);
+    for (int e = G.l; e < NZ; e += 16) {
+      const float v = (t < G.T) ? zp[e < NX ? e : e + 3] : 0.f;
+      if (e < NX) {
+        if (A.x_out) A.x_out[((size_t)b * A.Tm + t) * NX + e] = v;
+      } else {
+        A.u_out[((size_t)b * A.Tm + t) * NU + (e - NX)] = v;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void grp_write_state(const KArgs& A, const Grp& G, int n, int iters, uint32_t st, int done) {
+  if (G.l == 0) {
+    int* s = A.ws.state + (size_t)G.b * SW;
+    s[S_NOM] = n;
+    s[S_ITERS] = iters;
+    s[S_STATUS] = (int)st;
+    s[S_DONE] = done;
+    s[S_T] = G.T;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// persistent forward
+// ---------------------------------------------------------------------------
+
+template <bool DENSE>
+__global__ __launch_bounds__(64) void k_fwd_persistent(KArgs A) {
+  const int lane = threadIdx.x, grp = lane >> 4, l = lane & 15;
+  const LaneDir D = make_dir(A.P, (l == 0) ? 16 : l);
+  for (;;) {
+    int q = 0;
+    if (lane == 0) q = atomicAdd(A.ws.queue, 1);
+    q = __builtin_amdgcn_readfirstlane(q);
+    if (q >= A.nquads) break;
+    const Grp G = make_grp(A, q * 4 + grp, l);
+    if (!G.valid) continue;
+    uint32_t st = 0;
+    int n = 0, iters = 0;
+    if (G.T > 0) {
+      grp_init(A, G);
+      mem_fence_wg();
+      bool done = false;
+      for (int k = 0; k < A.K; ++k) {
+        if (done) continue;
+        grp_sweep<DENSE, 0, true>(A, G, n, k, D, st);
+        mem_fence_wg();
+        float J, dm, dsel;
+        grp_ls<DENSE>(A, G, n, J, dm);
+        mem_fence_wg();
+        const int best = ls_select(J, dm, dsel);
+        if (A.dlog && l == 0) A.dlog[((size_t)G.b * A.K + k) * (1 + A.Tm)] = best < 0 ? 255 : (uint8_t)best;
+        iters = k + 1;
+        if (best < 0) {
+          st |= ST_NONFINITE;
+        } else {
+          n = (n + 1 + best) % NSLOT;
+          if (A.tol > 0.f && dsel < A.tol) {
+            st |= ST_CONVERGED;
+            done = true;
+          }
+        }
+      }
+      if (A.tol > 0.f && !(st & ST_CONVERGED)) st |= ST_MAXITER;
+      if (A.need_grad) {
+        grp_sweep<DENSE, 1, true>(A, G, n, 0, D, st);
+      }
+    }
+    grp_outputs(A, G, n);
+    grp_write_state(A, G, n, iters, st, 1);
+    if (l == 0) A.status[G.b] = st | ((uint32_t)iters << DMPC_ST_ITERS_SHIFT);
+  }
+}
+
+__global__ void k_reset_queue(int* queue) {
+  if (threadIdx.x == 0) *queue = 0;
+}
+
+// counting sort of the instances by decreasing horizon (one workgroup)
+__global__ __launch_bounds__(1024) void k_sort_by_T(const int* T, int B, int Tm, int* order, int* queue) {
+  __shared__ int cnt[DMPC_T_LIMIT + 2];
+  for (int i = threadIdx.x; i <= Tm + 1; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    int t = T[b];
+    t = t < 0 ? 0 : (t > Tm ? Tm : t);
+    atomicAdd(&cnt[t], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int t = Tm; t >= 0; --t) {
+      const int c = cnt[t];
+      cnt[t] = run;
+      run += c;
+    }
+    *queue = 0;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    int t = T[b];
+    t = t < 0 ? 0 : (t > Tm ? Tm : t);
+    order[atomicAdd(&cnt[t], 1)] = b;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-launch form
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(64) void k_plain_init(KArgs A) {
+  const int lane = threadIdx.x, l = lane & 15;
+  const Grp G = make_grp(A, blockIdx.x * 4 + (lane >> 4), l);
+  if (!G.valid) return;
+  if (G.T > 0) grp_init(A, G);
+  grp_write_state(A, G, 0, 0, 0u, G.T > 0 ? 0 : 1);
+}
+
+// linearisation of every stage along the nominal: one 16-lane row per (b, t)
+__global__ __launch_bounds__(64) void k_plain_lin(KArgs A, int tail) {
+  const int lane = threadIdx.x, l = lane & 15, col = (l == 0) ? 16 : l;
+  const long long unit = (long long)blockIdx.x * 4 + (lane >> 4);
+  if (unit >= (long long)A.B * A.Tm) return;
+  const int b = (int)(unit / A.Tm), t = (int)(unit % A.Tm);
+  const int* s = A.ws.state + (size_t)b * SW;
+  const int T = s[S_T];
+  if (t + 1 >= T) return;
+  if (!tail && s[S_DONE]) return;
+  const int n = s[S_NOM];
+  float zb[NZ], Fc[NX];
+  load_z(traj_at(A, b, n, t), zb);
+  const LaneDir D = make_dir(A.P, col);
+  rk4_column(A.P, zb, zb + NX, D, Fc);
+  float* fp = lin_at(A, b, t) + col * 16;
+#pragma unroll
+  for (int k = 0; k < NX; ++k) fp[k] = Fc[k];
+}
+
+template <bool DENSE, int MODE>
+__global__ __launch_bounds__(64) void k_plain_riccati(KArgs A) {
+  const int lane = threadIdx.x, l = lane & 15;
+  const Grp G = make_grp(A, blockIdx.x * 4 + (lane >> 4), l);
+  if (!G.valid || G.T == 0) return;
+  int* s = A.ws.state + (size_t)G.b * SW;
+  if (MODE == 0 && s[S_DONE]) return;
+  uint32_t st = 0;
+  LaneDir D;  // unused: F comes from the linearisation buffer
+  grp_sweep<DENSE, MODE, false>(A, G, s[S_NOM], s[S_ITERS], D, st);
+  mem_fence_wg();
+  if (l == 0 && st) atomicOr((unsigned*)&s[S_STATUS], st);
+}
+
+template <bool DENSE>
+__global__ __launch_bounds__(64) void k_plain_ls(KArgs A) {
+  const int lane = threadIdx.x, l = lane & 15;
+  const Grp G = make_grp(A, blockIdx.x * 4 + (lane >> 4), l);
+  if (!G.valid || G.T == 0) return;
+  int* s = A.ws.state + (size_t)G.b * SW;
+  if (s[S_DONE]) return;
+  const int n = s[S_NOM], k = s[S_ITERS];
+  float J, dm, dsel;
+  grp_ls<DENSE>(A, G, n, J, dm);
+  mem_fence_wg();
+  const int best = ls_select(J, dm, dsel);
+  if (l == 0) {
+    if (A.dlog) A.dlog[((size_t)G.b * A.K + k) * (1 + A.Tm)] = best < 0 ? 255 : (uint8_t)best;
+    uint32_t st = (uint32_t)s[S_STATUS];
+    int done = 0, nn = n;
+    if (best < 0) {
+      st |= ST_NONFINITE;
+    } else {
+      nn = (n + 1 + best) % NSLOT;
+      if (A.tol > 0.f && dsel < A.tol) {
+        st |= ST_CONVERGED;
+        done = 1;
+      }
+    }
+    s[S_NOM] = nn;
+    s[S_ITERS] = k + 1;
+    s[S_STATUS] = (int)st;
+    s[S_DONE] = done;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_plain_finalize(KArgs A) {
+  const int lane = threadIdx.x, l = lane & 15;
+  const Grp G = make_grp(A, blockIdx.x * 4 + (lane >> 4), l);
+  if (!G.valid) return;
+  int* s = A.ws.state + (size_t)G.b * SW;
+  const int n = s[S_NOM], iters = s[S_ITERS];
+  uint32_t st = (uint32_t)s[S_STATUS];
+  if (A.tol > 0.f && G.T > 0 && !(st & ST_CONVERGED)) st |= ST_MAXITER;
+  grp_outputs(A, G, n);
+  mem_fence_wg();
+  if (l == 0) {
+    s[S_STATUS] = (int)st;
+    s[S_DONE] = 1;
+    A.status[G.b] = st | ((uint32_t)iters << DMPC_ST_ITERS_SHIFT);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward: Riccati adjoint at (x*, u*) with the forward's active set
+// ---------------------------------------------------------------------------
+
+__constant__ uint8_t c_pk_i[NPK];
+__constant__ uint8_t c_pk_j[NPK];
+
+template <bool DENSE>
+__global__ __launch_bounds__(64) void k_bwd(KArgs A) {
+  __shared__ float zz[4][2][20];
+  const int lane = threadIdx.x, grp = lane >> 4, l = lane & 15, col = (l == 0) ? 16 : l;
+  const int b = blockIdx.x * 4 + grp;
+  if (b >= A.B) return;
+  const int* s = A.ws.state + (size_t)b * SW;
+  const int T = s[S_T], n = s[S_NOM], Tm = A.Tm;
+  const int W = DENSE ? NPK : NZ;
+  float vrep[NX];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) vrep[i] = 0.f;
+  float vi = 0.f;
+  // backward vector sweep: q~ = d + F^T v, k~ = -M q~_u, v = q~_x + K^T q~_u
+  for (int t = T - 1; t >= 0; --t) {
+    const float* tp = tail_at(A, b, t);
+    const size_t srow = (size_t)b * Tm + t;
+    const float d_c = (col < NX) ? (A.gx ? A.gx[srow * NX + col] : 0.f) : A.gu[srow * NU + (col - NX)];
+    const float d_0 = A.gx ? A.gx[srow * NX] : 0.f;
+    const float* fc = tp + col * 16;
+    float qc = d_c;
+#pragma unroll
+    for (int k = 0; k < NX; ++k) qc = fmaf(fc[k], vrep[k], qc);
+    const float q0 = d_0 + vrep[0];
+    float qu[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) qu[a] = rb(qc, lane_of(NX + a));
+    const float* M = tp + FS + 52;
+    float kt[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc = fmaf(M[a * 4 + c], qu[c], acc);
+      kt[a] = -acc;
+    }
+    if (l == 0) *(float4*)(A.ws.ktil + srow * 4) = make_float4(kt[0], kt[1], kt[2], kt[3]);
+    vi = (l == 0) ? q0 : qc;
+    if (l < NX) {
+      const float4 kc = *(const float4*)(tp + FS + l * 4);
+      vi = fmaf(kc.x, qu[0], vi);
+      vi = fmaf(kc.y, qu[1], vi);
+      vi = fmaf(kc.z, qu[2], vi);
+      vi = fmaf(kc.w, qu[3], vi);
+    } else {
+      vi = 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < NX; ++j) vrep[j] = rb(vi, j);
+  }
+  if (l < NX) A.gx0[(size_t)b * NX + l] = (T > 0) ? vi : 0.f;
+  mem_fence_wg();
+  // forward sweep: u~ = K x~ + k~, x~' = A x~ + B u~;  dL/dc = z~, dL/dC from z~ and z*
+  float xt[NX];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) xt[i] = 0.f;
+  for (int t = 0; t < Tm; ++t) {
+    const size_t srow = (size_t)b * Tm + t;
+    if (t < T) {
+      const float* tp = tail_at(A, b, t);
+      const float4 kk = *(const float4*)(A.ws.ktil + srow * 4);
+      float ut[4] = {kk.x, kk.y, kk.z, kk.w};
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        const float4 kj = *(const float4*)(tp + FS + j * 4);
+        ut[0] = fmaf(kj.x, xt[j], ut[0]);
+        ut[1] = fmaf(kj.y, xt[j], ut[1]);
+        ut[2] = fmaf(kj.z, xt[j], ut[2]);
+        ut[3] = fmaf(kj.w, xt[j], ut[3]);
+      }
+      float zs[NZ];
+      load_z(traj_at(A, b, n, t), zs);
+      if (l == 0) {
+        float* zt = zz[grp][0];
+        float* zr = zz[grp][1];
+        for (int i = 0; i < NX; ++i) zt[i] = xt[i];
+        for (int a = 0; a < NU; ++a) zt[NX + a] = ut[a];
+        for (int i = 0; i < NZ; ++i) zr[i] = zs[i];
+      }
+      mem_fence_wg();
+      __builtin_amdgcn_wave_barrier();
+      const float* zt = zz[grp][0];
+      const float* zr = zz[grp][1];
+      for (int e = l; e < NZ; e += 16) A.gp[srow * NZ + e] = zt[e];
+      if (!DENSE) {
+        for (int e = l; e < NZ; e += 16) A.gQ[srow * NZ + e] = zt[e] * zr[e];
+      } else {
+        for (int m = l; m < NPK; m += 16) {
+          const int i = c_pk_i[m], j = c_pk_j[m];
+          A.gQ[srow * NPK + m] = (i == j) ? zt[i] * zr[i] : zt[i] * zr[j] + zt[j] * zr[i];
+        }
+      }
+      mem_fence_wg();
+      __builtin_amdgcn_wave_barrier();
+      if (t + 1 < T) {
+        float xi = 0.f;
+        if (l < NX) {
+          // row l of F = [A | B]: column c stored at c * 16
+#pragma unroll
+          for (int c = 0; c < NX; ++c) xi = fmaf(tp[c * 16 + l], xt[c], xi);
+#pragma unroll
+          for (int a = 0; a < NU; ++a) xi = fmaf(tp[(NX + a) * 16 + l], ut[a], xi);
+        }
+#pragma unroll
+        for (int j = 0; j < NX; ++j) xt[j] = rb(xi, j);
+      }
+    } else {
+      for (int e = l; e < NZ; e += 16) A.gp[srow * NZ + e] = 0.f;
+      for (int m = l; m < W; m += 16) A.gQ[srow * W + m] = 0.f;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+struct Layout {
+  size_t state, queue, order, traj, gains, lin, tail, ktil, total;
+};
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int check_cfg(const dmpc_config* c) {
+  if (!c) return DMPC_EINVAL;
+  if (c->B < 0 || c->T_max < 1 || c->max_iter < 0) return DMPC_EINVAL;
+  if (c->T_max > DMPC_T_LIMIT || c->max_iter > DMPC_K_LIMIT) return DMPC_EUNSUPPORTED;
+  if (c->cost_kind != DMPC_COST_DIAG && c->cost_kind != DMPC_COST_DENSE) return DMPC_EUNSUPPORTED;
+  if (c->ckpt_every != 0) return DMPC_EUNSUPPORTED;
+  if (!(c->tol_du == c->tol_du) || !(c->fp64_pivot == c->fp64_pivot)) return DMPC_EINVAL;
+  if (c->flags & ~(DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT)) return DMPC_EINVAL;
+  return DMPC_OK;
+}
+
+Layout make_layout(const dmpc_config* c) {
+  Layout L;
+  const size_t B = (size_t)c->B, Tm = (size_t)c->T_max;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.state = take(B * SW * sizeof(int));
+  L.queue = take(256);
+  L.order = take(B * sizeof(int));
+  L.traj = take(B * NSLOT * Tm * ZS * sizeof(float));
+  L.gains = take(B * Tm * GS * sizeof(float));
+  L.lin = (c->flags & DMPC_PLAIN) ? take(B * Tm * FS * sizeof(float)) : take(0);
+  const bool g = (c->flags & DMPC_NEED_GRAD) != 0;
+  L.tail = take(g ? B * Tm * TS * sizeof(float) : 0);
+  L.ktil = take(g ? B * Tm * 4 * sizeof(float) : 0);
+  L.total = off;
+  return L;
+}
+
+Dyn make_dyn(const dmpc_quad_params& q) {
+  Dyn P;
+  P.h = q.dt;
+  P.h2 = 0.5f * q.dt;
+  P.h6 = q.dt / 6.f;
+  P.g = q.g;
+  P.inv_m = 1.f / q.mass;
+  P.arm_a = q.arm / sqrtf(2.f);
+  P.kappa = q.kappa;
+  P.iJx = 1.f / q.Jxx;
+  P.iJy = 1.f / q.Jyy;
+  P.iJz = 1.f / q.Jzz;
+  P.cx = (q.Jzz - q.Jyy) / q.Jxx;
+  P.cy = (q.Jxx - q.Jzz) / q.Jyy;
+  P.cz = (q.Jyy - q.Jxx) / q.Jzz;
+  P.hover = q.mass * q.g / 4.f;
+  return P;
+}
+
+thread_local std::string g_err;
+
+}  // namespace
+
+struct dmpc_handle_s {
+  int device = 0;
+  int cu = 0;
+  int occ[2] = {1, 1};
+  int last_launches = 0;
+  std::string err;
+};
+
+namespace {
+
+int fail(dmpc_handle h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  g_err = msg;
+  return code;
+}
+
+int hip_check(dmpc_handle h, hipError_t e, const char* what) {
+  if (e == hipSuccess) return DMPC_OK;
+  return fail(h, DMPC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool pk_ready = false;
+
+int upload_pack_tables(dmpc_handle h) {
+  if (pk_ready) return DMPC_OK;
+  uint8_t pi[NPK], pj[NPK];
+  int m = 0;
+  for (int i = 0; i < NZ; ++i)
+    for (int j = i; j < NZ; ++j) {
+      pi[m] = (uint8_t)i;
+      pj[m] = (uint8_t)j;
+      ++m;
+    }
+  int rc = hip_check(h, hipMemcpyToSymbol(HIP_SYMBOL(c_pk_i), pi, sizeof pi), "pack table");
+  if (rc) return rc;
+  rc = hip_check(h, hipMemcpyToSymbol(HIP_SYMBOL(c_pk_j), pj, sizeof pj), "pack table");
+  if (rc) return rc;
+  pk_ready = true;
+  return DMPC_OK;
+}
+
+KArgs base_args(const dmpc_config* c, void* workspace) {
+  KArgs A;
+  std::memset(&A, 0, sizeof A);
+  const Layout L = make_layout(c);
+  char* w = (char*)workspace;
+  A.B = c->B;
+  A.Tm = c->T_max;
+  A.K = c->max_iter;
+  A.tol = c->tol_du;
+  A.piv = c->fp64_pivot;
+  A.need_grad = (c->flags & DMPC_NEED_GRAD) ? 1 : 0;
+  A.nquads = (c->B + 3) / 4;
+  A.ws.state = (int*)(w + L.state);
+  A.ws.queue = (int*)(w + L.queue);
+  A.ws.order = (int*)(w + L.order);
+  A.ws.traj = (float*)(w + L.traj);
+  A.ws.gains = (float*)(w + L.gains);
+  A.ws.lin = (float*)(w + L.lin);
+  A.ws.tail = (float*)(w + L.tail);
+  A.ws.ktil = (float*)(w + L.ktil);
+  return A;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dmpc_validate(const dmpc_config* cfg) {
+  const int rc = check_cfg(cfg);
+  if (rc) g_err = "invalid configuration";
+  return rc;
+}
+
+size_t dmpc_workspace_bytes(const dmpc_config* cfg) {
+  if (check_cfg(cfg)) return 0;
+  return make_layout(cfg).total;
+}
+
+int dmpc_create(dmpc_handle* out, int device) {
+  if (!out) return fail(nullptr, DMPC_EINVAL, "NULL handle pointer");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+    return fail(nullptr, DMPC_EHIP, "no such HIP device");
+  dmpc_handle h = new dmpc_handle_s();
+  h->device = device;
+  hipDeviceProp_t prop;
+  int rc = hip_check(h, hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  h->cu = prop.multiProcessorCount;
+  (void)hipSetDevice(device);
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fwd_persistent<false>, 64, 0) == hipSuccess && occ > 0)
+    h->occ[0] = occ;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fwd_persistent<true>, 64, 0) == hipSuccess && occ > 0)
+    h->occ[1] = occ;
+  rc = upload_pack_tables(h);
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return DMPC_OK;
+}
+
+int dmpc_destroy(dmpc_handle h) {
+  delete h;
+  return DMPC_OK;
+}
+
+const char* dmpc_last_error(dmpc_handle h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+int dmpc_last_launch_count(dmpc_handle h) { return h ? h->last_launches : -1; }
+
+int dmpc_forward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* x0, const float* Q,
+                 const float* p, const float* u_lo, const float* u_hi, const int32_t* T, float* u_out,
+                 float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes, uint8_t* decision_log,
+                 void* stream) {
+  if (!h) return fail(nullptr, DMPC_EINVAL, "NULL handle");
+  int rc = check_cfg(cfg);
+  if (rc) return fail(h, rc, "invalid configuration");
+  h->last_launches = 0;
+  if (cfg->B == 0) return DMPC_OK;
+  if (!x0 || !Q || !p || !u_lo || !u_hi || !u_out || !status)
+    return fail(h, DMPC_EINVAL, "NULL required pointer");
+  if (!(dyn.mass > 0.f) || !(dyn.Jxx > 0.f) || !(dyn.Jyy > 0.f) || !(dyn.Jzz > 0.f) || !(dyn.dt > 0.f))
+    return fail(h, DMPC_EINVAL, "non-positive mass, inertia or step");
+  const Layout L = make_layout(cfg);
+  if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace & 255))
+    return fail(h, DMPC_EWORKSPACE, "workspace missing, misaligned or smaller than dmpc_workspace_bytes()");
+  rc = hip_check(h, hipSetDevice(h->device), "hipSetDevice");
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  KArgs A = base_args(cfg, workspace);
+  A.P = make_dyn(dyn);
+  A.x0 = x0;
+  A.Q = Q;
+  A.p = p;
+  A.lo = u_lo;
+  A.hi = u_hi;
+  A.T = T;
+  A.u_out = u_out;
+  A.x_out = x_out;
+  A.status = status;
+  A.dlog = decision_log;
+  const bool dense = cfg->cost_kind == DMPC_COST_DENSE;
+  const int nq = A.nquads;
+  int launches = 0;
+  if (cfg->flags & DMPC_PLAIN) {
+    const long long units = (long long)cfg->B * cfg->T_max;
+    const int lin_grid = (int)((units + 3) / 4);
+    k_plain_init<<<nq, 64, 0, s>>>(A);
+    ++launches;
+    for (int k = 0; k < cfg->max_iter; ++k) {
+      k_plain_lin<<<lin_grid, 64, 0, s>>>(A, 0);
+      if (dense) k_plain_riccati<true, 0><<<nq, 64, 0, s>>>(A);
+      else k_plain_riccati<false, 0><<<nq, 64, 0, s>>>(A);
+      if (dense) k_plain_ls<true><<<nq, 64, 0, s>>>(A);
+      else k_plain_ls<false><<<nq, 64, 0, s>>>(A);
+      launches += 3;
+    }
+    if (A.need_grad) {
+      k_plain_lin<<<lin_grid, 64, 0, s>>>(A, 1);
+      if (dense) k_plain_riccati<true, 1><<<nq, 64, 0, s>>>(A);
+      else k_plain_riccati<false, 1><<<nq, 64, 0, s>>>(A);
+      launches += 2;
+    }
+    k_plain_finalize<<<nq, 64, 0, s>>>(A);
+    ++launches;
+  } else {
+    const bool lpt = (cfg->flags & DMPC_LPT) && T;
+    if (lpt) {
+      A.use_order = 1;
+      k_sort_by_T<<<1, 1024, 0, s>>>(T, cfg->B, cfg->T_max, A.ws.order, A.ws.queue);
+    } else {
+      k_reset_queue<<<1, 64, 0, s>>>(A.ws.queue);
+    }
+    const int cap = std::max(1, h->cu * h->occ[dense ? 1 : 0]);
+    const int grid = std::min(nq, cap);
+    if (dense) k_fwd_persistent<true><<<grid, 64, 0, s>>>(A);
+    else k_fwd_persistent<false><<<grid, 64, 0, s>>>(A);
+    launches += 2;
+  }
+  h->last_launches = launches;
+  return hip_check(h, hipGetLastError(), "kernel launch");
+}
+
+int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, const void* workspace, size_t workspace_bytes,
+                  const float* grad_u, const float* grad_x, float* grad_Q, float* grad_p, float* grad_x0,
+                  void* stream) {
+  if (!h) return fail(nullptr, DMPC_EINVAL, "NULL handle");
+  int rc = check_cfg(cfg);
+  if (rc) return fail(h, rc, "invalid configuration");
+  h->last_launches = 0;
+  if (!(cfg->flags & DMPC_NEED_GRAD)) return fail(h, DMPC_EINVAL, "backward needs a forward run with DMPC_NEED_GRAD");
+  if (cfg->B == 0) return DMPC_OK;
+  if (!grad_u || !grad_Q || !grad_p || !grad_x0) return fail(h, DMPC_EINVAL, "NULL required pointer");
+  const Layout L = make_layout(cfg);
+  if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace & 255))
+    return fail(h, DMPC_EWORKSPACE, "workspace missing, misaligned or smaller than dmpc_workspace_bytes()");
+  rc = hip_check(h, hipSetDevice(h->device), "hipSetDevice");
+  if (rc) return rc;
+  KArgs A = base_args(cfg, (void*)workspace);
+  A.gu = grad_u;
+  A.gx = grad_x;
+  A.gQ = grad_Q;
+  A.gp = grad_p;
+  A.gx0 = grad_x0;
+  hipStream_t s = (hipStream_t)stream;
+  if (cfg->cost_kind == DMPC_COST_DENSE) k_bwd<true><<<A.nquads, 64, 0, s>>>(A);
+  else k_bwd<false><<<A.nquads, 64, 0, s>>>(A);
+  h->last_launches = 1;
+  return hip_check(h, hipGetLastError(), "kernel launch");
+}
+
+int dmpc_capture_begin(dmpc_handle h, void* stream) {
+  if (!h) return fail(nullptr, DMPC_EINVAL, "NULL handle");
+  return hip_check(h, hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal), "begin capture");
+}
+
+int dmpc_capture_end(dmpc_handle h, void* stream, void** graph_exec) {
+  if (!h || !graph_exec) return fail(h, DMPC_EINVAL, "NULL argument");
+  hipGraph_t g = nullptr;
+  int rc = hip_check(h, hipStreamEndCapture((hipStream_t)stream, &g), "end capture");
+  if (rc) return rc;
+  hipGraphExec_t e = nullptr;
+  rc = hip_check(h, hipGraphInstantiate(&e, g, nullptr, nullptr, 0), "graph instantiate");
+  (void)hipGraphDestroy(g);
+  if (rc) return rc;
+  *graph_exec = (void*)e;
+  return DMPC_OK;
+}
+
+int dmpc_graph_launch(dmpc_handle h, void* graph_exec, void* stream) {
+  if (!h || !graph_exec) return fail(h, DMPC_EINVAL, "NULL argument");
+  return hip_check(h, hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream), "graph launch");
+}
+
+int dmpc_graph_destroy(dmpc_handle h, void* graph_exec) {
+  if (!graph_exec) return DMPC_OK;
+  return hip_check(h, hipGraphExecDestroy((hipGraphExec_t)graph_exec), "graph destroy");
+}
+
+}  // extern "C"

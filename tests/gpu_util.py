@@ -1,0 +1,116 @@
+"""Helpers for the GPU parity tests: run the HIP library through its C ABI and
+compare with the FP64 oracle, which replays the kernel's discrete decisions
+(line-search choice, box-QP clamp patterns, iteration count, final active
+set) so that the comparison isolates arithmetic from decisions."""
+import numpy as np
+
+import oracle as orc
+import workloads as W
+
+_handle = None
+
+
+def handle():
+    global _handle
+    import paper_2605_29155_amd as D
+    if _handle is None:
+        _handle = D.Handle(0)
+    return _handle
+
+
+def rel(a, b, axis_from=1):
+    """Per-instance normwise relative error ||a - b||_2 / max(||b||_2, 1e-6)."""
+    a = np.asarray(a, np.float64).reshape(a.shape[0], -1)
+    b = np.asarray(b, np.float64).reshape(b.shape[0], -1)
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-6)
+
+
+def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=True, grad_u=None, grad_x=None,
+            fp64_pivot=1e-6):
+    import torch
+
+    import paper_2605_29155_amd as D
+    dev = "cuda:0"
+    h = handle()
+    B, Tm = d["B"], d["T_max"]
+    K = d["K"] if K is None else K
+    tol = d["tol"] if tol is None else tol
+    flags = (D.NEED_GRAD if need_grad else 0) | (D.PLAIN if plain else 0) | (D.LPT if lpt else 0)
+    cfg = D.make_config(B, Tm, d["cost_kind"], K, tol, flags, fp64_pivot)
+    t = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev) for k in ("x0", "Q", "p", "lo", "hi")}
+    Tt = torch.from_numpy(d["T"].astype(np.int32)).to(dev)
+    ws = D.alloc_workspace(cfg, dev)
+    u = torch.full((B, Tm, 4), float("nan"), device=dev)
+    x = torch.full((B, Tm, 13), float("nan"), device=dev)
+    st = torch.zeros(B, dtype=torch.int32, device=dev)
+    dl = torch.zeros((B, max(K, 1), 1 + Tm), dtype=torch.uint8, device=dev) if dlog else None
+    D.forward_raw(h, cfg, D.quad_params(W.quad_params_f32()), t["x0"], t["Q"], t["p"], t["lo"], t["hi"], Tt, u, x,
+                  st, ws, dl)
+    out = dict(launches_fwd=h.launch_count())
+    if need_grad:
+        gu = torch.from_numpy(np.ascontiguousarray(d["grad_u"] if grad_u is None else grad_u)).to(dev)
+        gx = None if grad_x is None else torch.from_numpy(np.ascontiguousarray(grad_x)).to(dev)
+        gQ = torch.full_like(t["Q"], float("nan"))
+        gp = torch.full_like(t["p"], float("nan"))
+        gx0 = torch.full_like(t["x0"], float("nan"))
+        D.backward_raw(h, cfg, ws, gu, gx, gQ, gp, gx0)
+        out["launches_bwd"] = h.launch_count()
+    torch.cuda.synchronize()
+    out.update(u=u.cpu().numpy(), x=x.cpu().numpy(), status=st.cpu().numpy().astype(np.uint32), K=K)
+    if dlog:
+        out["dlog"] = dl.cpu().numpy()
+    if need_grad:
+        out.update(dQ=gQ.cpu().numpy(), dp=gp.cpu().numpy(), dx0=gx0.cpu().numpy())
+    return out
+
+
+def oracle_replay(d, g, idx=None, grad_u=None, grad_x=None):
+    """FP64 oracle on the same inputs, replaying the kernel's decisions; also a
+    free oracle run for the decision-agreement rate."""
+    P = orc.params_from(W.quad_params_f32())
+    sel = slice(None) if idx is None else idx
+    x0, Q, p, lo, hi, T = (np.asarray(d[k])[sel] for k in ("x0", "Q", "p", "lo", "hi", "T"))
+    gu = np.asarray(d["grad_u"] if grad_u is None else grad_u)[sel]
+    gx = None if grad_x is None else np.asarray(grad_x)[sel]
+    K = g["K"]
+    iters = ((g["status"][sel] >> 8) & 255).astype(np.int32)
+    dl = g["dlog"][sel]
+    alpha, pattern = dl[:, :K, 0], dl[:, :K, 1:]
+    fr = orc.forward(P, x0, Q, p, lo, hi, T, K=K, replay=(iters, alpha, pattern))
+    ff = orc.forward(P, x0, Q, p, lo, hi, T, K=K, tol=d["tol"])
+    out = dict(replay=fr, free=ff, iters=iters, alpha=alpha, pattern=pattern)
+    if "dQ" in g:
+        mask = orc.active_mask(g["u"][sel], lo, hi, T)
+        out["bwd"] = orc.backward(P, x0, Q, p, lo, hi, fr["u"], fr["x"], gu, gx, T=T, mask=mask)
+    return out
+
+
+def decision_agreement(g, o, idx=None):
+    """Fraction of instances whose free-run oracle decisions (alpha per
+    iteration, box-QP patterns, iteration count) equal the kernel's."""
+    sel = slice(None) if idx is None else idx
+    ff = o["free"]
+    K = g["K"]
+    same = np.ones(len(o["iters"]), bool)
+    same &= ff["iters"] == o["iters"]
+    for b in range(len(same)):
+        k = o["iters"][b]
+        same[b] &= np.array_equal(ff["alpha"][b, :k], o["alpha"][b, :k])
+        same[b] &= np.array_equal(ff["pattern"][b, :k], o["pattern"][b, :k])
+    return same.mean()
+
+
+def alpha_choices_valid(o, rtol=1e-4):
+    """Every kernel line-search choice is a minimiser of the oracle's candidate
+    costs up to rounding (the choice is a floating-point decision)."""
+    cc = o["replay"]["cand_cost"]
+    bad = 0
+    for b in range(cc.shape[0]):
+        for k in range(o["iters"][b]):
+            a = o["alpha"][b, k]
+            if a == 255:
+                continue
+            m = np.min(cc[b, k])
+            if cc[b, k, a] > m + rtol * (1 + abs(m)):
+                bad += 1
+    return bad

@@ -1,0 +1,121 @@
+"""GPU parity of the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances (per-instance normwise relative error): 1e-4 on u*, 1e-3 on the
+gradients dL/dQ, dL/dp, dL/dx0.  The oracle replays the kernel's discrete
+decisions (line-search index, box-QP clamp patterns, iteration count, final
+active set), each of which the kernel takes in FP32; the tests also check
+that those decisions are valid for the oracle (the chosen candidate is a
+minimiser up to rounding) and report how often a free FP64 run takes the same
+ones.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+from gpu_util import alpha_choices_valid, decision_agreement, oracle_replay, rel, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL_U, TOL_G = 1e-4, 1e-3
+
+
+def check_parity(d, g, o, label, check_grad=True):
+    T = d["T"]
+    eu = rel(g["u"], o["replay"]["u"])
+    ex = rel(g["x"], o["replay"]["x"])
+    msg = "%s: u* max %.2e p99 %.2e | x* max %.2e" % (label, eu.max(), np.percentile(eu, 99), ex.max())
+    if check_grad and "bwd" in o:
+        eQ, ep, e0 = rel(g["dQ"], o["bwd"]["dQ"]), rel(g["dp"], o["bwd"]["dp"]), rel(g["dx0"], o["bwd"]["dx0"])
+        msg += " | dQ %.2e dp %.2e dx0 %.2e" % (eQ.max(), ep.max(), e0.max())
+    agree = decision_agreement(g, o)
+    msg += " | decisions agree %.4f" % agree
+    print(msg, flush=True)
+    assert eu.max() <= TOL_U, msg
+    if check_grad and "bwd" in o:
+        assert eQ.max() <= TOL_G and ep.max() <= TOL_G and e0.max() <= TOL_G, msg
+    assert alpha_choices_valid(o) == 0
+    # controls inside the box, padding zero
+    lo, hi = d["lo"][:, None, :], d["hi"][:, None, :]
+    assert np.all(g["u"] >= lo - 0) and np.all(g["u"] <= hi)
+    pad = np.arange(d["T_max"])[None, :] >= T[:, None]
+    assert np.all(g["u"][pad] == 0) and np.all(g["x"][pad] == 0)
+    return agree
+
+
+@pytest.mark.parametrize("plain", [False, True], ids=["persistent", "plain"])
+def test_cfg0_parity(plain):
+    d = W.make(0)
+    g = run_gpu(d, plain=plain)
+    o = oracle_replay(d, g)
+    check_parity(d, g, o, "cfg0 " + ("plain" if plain else "persistent"))
+    assert g["launches_fwd"] == (3 * d["K"] + 4 if plain else 2)
+    assert g["launches_bwd"] == 1
+
+
+def test_cfg0_small_pu_parity():
+    # p_u scaled by 0.01: non-trivial free sets in the box-QP
+    d = W.make(0, pu_scale=0.01, seed=2000)
+    g = run_gpu(d)
+    o = oracle_replay(d, g)
+    check_parity(d, g, o, "cfg0 pu*0.01")
+
+
+def test_ragged_edge_cases():
+    # B not a multiple of 4; horizons 0, 1, 2 and T_max; tolerance-based stop
+    d = W.make(3, B=7, T=12)
+    d["T"] = np.array([0, 1, 2, 12, 5, 12, 3], np.int32)
+    pad = np.arange(12)[None, :] >= d["T"][:, None]
+    d["Q"][pad] = 0
+    d["p"][pad] = 0
+    d["grad_u"][pad] = 0
+    g = run_gpu(d)
+    o = oracle_replay(d, g)
+    check_parity(d, g, o, "ragged edge")
+    assert g["status"][0] == 0 and np.all(g["dx0"][0] == 0) and np.all(g["dp"][0] == 0)
+
+
+def test_cfg1_parity_full_size():
+    d = W.make(1)
+    g = run_gpu(d, need_grad=False)
+    o = oracle_replay(d, g)
+    agree = check_parity(d, g, o, "cfg1 B=1024 T=20", check_grad=False)
+    assert agree >= 0.9
+
+
+def test_persistent_equals_plain():
+    d = W.make(1, B=64)
+    a = run_gpu(d)
+    b = run_gpu(d, plain=True)
+    assert np.array_equal(a["dlog"], b["dlog"])
+    assert rel(a["u"], b["u"]).max() <= 1e-6
+    assert rel(a["dp"], b["dp"]).max() <= 1e-5
+
+
+def test_deterministic_and_lpt_invariant():
+    d = W.make(3, B=64, T=20)
+    a = run_gpu(d, lpt=True)
+    b = run_gpu(d, lpt=True)
+    c = run_gpu(d, lpt=False)
+    for k in ("u", "x", "dQ", "dp", "dx0", "status", "dlog"):
+        assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], c[k]), k
+
+
+def test_nonfinite_input_is_flagged():
+    d = W.make(0, B=4)
+    d["x0"][1, 0] = np.nan
+    g = run_gpu(d)
+    assert g["status"][1] & 0x4
+    assert np.all(np.isfinite(g["u"][0])) and np.all(np.isfinite(g["u"][2]))
+
+
+def test_fixed_control_bounds():
+    # lo == hi on some rotors: those controls are always active
+    d = W.make(0, B=4)
+    d["lo"][:, 1] = 2.0
+    d["hi"][:, 1] = 2.0
+    g = run_gpu(d)
+    assert np.all(g["u"][:, :, 1] == 2.0)
+    o = oracle_replay(d, g)
+    check_parity(d, g, o, "fixed rotor")
