@@ -55,7 +55,7 @@ def lib():
         L.dmpc_validate.argtypes = [C.POINTER(Config)]
         L.dmpc_workspace_bytes.argtypes = [C.POINTER(Config)]
         L.dmpc_workspace_bytes.restype = sz
-        L.dmpc_forward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 10 + [vp, sz, vp, vp]
+        L.dmpc_forward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 9 + [vp, sz, vp, vp]
         L.dmpc_backward.argtypes = [vp, C.POINTER(Config), vp, sz] + [vp] * 5 + [vp]
         L.dmpc_last_launch_count.argtypes = [vp]
         L.dmpc_capture_begin.argtypes = [vp, vp]

@@ -162,75 +162,81 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, const La
       for (int k = 0; k < NX; ++k) Fc[k] = 0.f;
     }
 
+    // Stage algebra, accumulated in FP64 from FP32 operands (products of two
+    // floats are exact in double): without it the Schur-complement update of V
+    // loses several digits on these costs.
     // Y[:, col] = V F[:, col]   (V symmetric: lane k's row k is column k)
-    float Yc[NX];
-#pragma unroll
-    for (int i = 0; i < NX; ++i) Yc[i] = 0.f;
+    double Fd[NX], Yc[NX];
 #pragma unroll
     for (int k = 0; k < NX; ++k) {
-      const float f = Fc[k];
+      Fd[k] = (double)Fc[k];
+      Yc[k] = 0.0;
+    }
 #pragma unroll
-      for (int i = 0; i < NX; ++i) Yc[i] = fmaf(rb(Vr[i], k), f, Yc[i]);
+    for (int k = 0; k < NX; ++k) {
+      const double f = Fd[k];
+#pragma unroll
+      for (int i = 0; i < NX; ++i) Yc[i] = fma((double)rb(Vr[i], k), f, Yc[i]);
     }
     // Q[:, col] = (F^T V F)[:, col]; F[:, 0] = e_0
-    float Qc[NZ];
+    double Qc[NZ];
     Qc[0] = Yc[0];
 #pragma unroll
     for (int i = 1; i < NZ; ++i) {
-      float s = 0.f;
+      double s = 0.0;
 #pragma unroll
-      for (int k = 0; k < NX; ++k) s = fmaf(rb(Fc[k], lane_of(i)), Yc[k], s);
+      for (int k = 0; k < NX; ++k) s = fma((double)rb(Fc[k], lane_of(i)), Yc[k], s);
       Qc[i] = s;
     }
     // row 0 of F^T V F, gathered (only lane 0 uses it: its own column is 16)
-    float R0[NZ];
-    R0[0] = Vr[0];
+    double R0[NZ];
+    R0[0] = (double)Vr[0];
 #pragma unroll
-    for (int j = 1; j < NZ; ++j) R0[j] = rb(Yc[0], lane_of(j));
+    for (int j = 1; j < NZ; ++j) R0[j] = rb64(Yc[0], lane_of(j));
 
     // stage cost: Q += C_t, q = g + F^T v with g = C_t z + c_t
-    float qc, q0, Hd[4] = {0.f, 0.f, 0.f, 0.f};
+    double qc, q0, Hd[4] = {0.0, 0.0, 0.0, 0.0};
     {
       const size_t srow = (size_t)b * A.Tm + t;
       const float* prow = A.p + srow * NZ;
-      const float zb_c = zp[col < NX ? col : col + 3];
+      const double zb_c = (double)zp[col < NX ? col : col + 3];
       if (!DENSE) {
         const float* qrow = A.Q + srow * NZ;
-        const float qd_c = qrow[col], qd_0 = qrow[0];
-        qc = fmaf(qd_c, zb_c, prow[col]);
-        q0 = fmaf(qd_0, zb[0], prow[0]);
+        const double qd_c = (double)qrow[col], qd_0 = (double)qrow[0];
+        qc = fma(qd_c, zb_c, (double)prow[col]);
+        q0 = fma(qd_0, (double)zb[0], (double)prow[0]);
 #pragma unroll
-        for (int i = 1; i < NX; ++i) Qc[i] += (i == col) ? qd_c : 0.f;
+        for (int i = 1; i < NX; ++i) Qc[i] += (i == col) ? qd_c : 0.0;
         R0[0] += qd_0;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) Hd[a] = qrow[NX + a];
+        for (int a = 0; a < 4; ++a) Hd[a] = (double)qrow[NX + a];
       } else {
         const float* crow = A.Q + srow * NPK;
-        float gc = prow[col], g0 = prow[0];
+        double gc = (double)prow[col], g0 = (double)prow[0];
 #pragma unroll
         for (int i = 0; i < NZ; ++i) {
-          const float cc = crow[i <= col ? pidx(i, col) : pidx(col, i)];
-          const float c0 = crow[i];
+          const double cc = (double)crow[i <= col ? pidx(i, col) : pidx(col, i)];
+          const double c0 = (double)crow[i];
           Qc[i] += cc;
           R0[i] += c0;
-          gc = fmaf(cc, zb[i], gc);
-          g0 = fmaf(c0, zb[i], g0);
+          gc = fma(cc, (double)zb[i], gc);
+          g0 = fma(c0, (double)zb[i], g0);
         }
         qc = gc;
         q0 = g0;
       }
     }
 #pragma unroll
-    for (int k = 0; k < NX; ++k) qc = fmaf(Fc[k], vrep[k], qc);
-    q0 += vrep[0];
+    for (int k = 0; k < NX; ++k) qc = fma(Fd[k], (double)vrep[k], qc);
+    q0 += (double)vrep[0];
 
     // replicate the control block: H = Q_uu (upper triangle from column b), q_u
-    float H[16], qu[4];
+    double H[16], qu[4];
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) {
 #pragma unroll
       for (int a = 0; a <= bb; ++a) {
-        const float v = rb(Qc[NX + a], lane_of(NX + bb));
+        const double v = rb64(Qc[NX + a], lane_of(NX + bb));
         H[a * 4 + bb] = v;
         H[bb * 4 + a] = v;
       }
@@ -238,20 +244,20 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, const La
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       H[a * 5] += Hd[a];
-      qu[a] = rb(qc, lane_of(NX + a));
+      qu[a] = rb64(qc, lane_of(NX + a));
     }
-    float dl[4], dh[4];
+    double dl[4], dh[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      dl[a] = G.lo[a] - zb[NX + a];
-      dh[a] = G.hi[a] - zb[NX + a];
+      dl[a] = (double)G.lo[a] - (double)zb[NX + a];
+      dh[a] = (double)G.hi[a] - (double)zb[NX + a];
     }
 
-    float kv[4] = {0.f, 0.f, 0.f, 0.f}, fr[4];
+    double kv[4] = {0.0, 0.0, 0.0, 0.0}, fr[4];
     Chol4 C;
     float* gp = gains_at(A, b, t);
     if (MODE == 0) {
-      float kw[4] = {0.f, 0.f, 0.f, 0.f};
+      double kw[4] = {0.0, 0.0, 0.0, 0.0};
       if (kit > 0) {
         const float4 w = *(const float4*)(gp + 52);
         kw[0] = w.x; kw[1] = w.y; kw[2] = w.z; kw[3] = w.w;
@@ -259,48 +265,49 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, const La
       boxqp(H, qu, dl, dh, kw, A.piv, kv, fr, C, st);
     } else {
 #pragma unroll
-      for (int a = 0; a < 4; ++a) fr[a] = (zb[NX + a] == G.lo[a] || zb[NX + a] == G.hi[a]) ? 0.f : 1.f;
+      for (int a = 0; a < 4; ++a) fr[a] = (zb[NX + a] == G.lo[a] || zb[NX + a] == G.hi[a]) ? 0.0 : 1.0;
       chol4(H, fr, A.piv, C, st);
     }
 
     // gain column: K[:, l] = -Qff^{-1} Q_ux[:, l] on the free rows, 0 on clamped rows
-    float Qux[4], Kc[4];
+    double Qux[4], Kd[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       Qux[a] = (l == 0) ? R0[NX + a] : Qc[NX + a];
-      Kc[a] = fr[a] * Qux[a];
+      Kd[a] = fr[a] * Qux[a];
     }
-    solve4(C, Kc);
+    solve4(C, Kd);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) Kc[a] = -Kc[a];
+    for (int a = 0; a < 4; ++a) Kd[a] = -Kd[a];
+    const float Kc[4] = {(float)Kd[0], (float)Kd[1], (float)Kd[2], (float)Kd[3]};
 
     // V row l = Q_xx[l, :] + Q_ux[:, l]^T K ;  v_l = Q_x[l] + Q_ux[:, l]^T k
-    float Vn[NX];
+    double Vn[NX];
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      float s = (l == 0) ? R0[j] : Qc[j];
+      double s = (l == 0) ? R0[j] : Qc[j];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) s = fmaf(Qux[a], rb(Kc[a], j), s);
+      for (int a = 0; a < 4; ++a) s = fma(Qux[a], rb64(Kd[a], j), s);
       Vn[j] = s;
     }
-    float vi = (l == 0) ? q0 : qc;
+    double vi = (l == 0) ? q0 : qc;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) vi = fmaf(Qux[a], kv[a], vi);
+    for (int a = 0; a < 4; ++a) vi = fma(Qux[a], kv[a], vi);
     const bool xl = l < NX;
 #pragma unroll
-    for (int j = 0; j < NX; ++j) Vr[j] = xl ? Vn[j] : 0.f;
-    vi = xl ? vi : 0.f;
+    for (int j = 0; j < NX; ++j) Vr[j] = xl ? (float)Vn[j] : 0.f;
+    const float vf = xl ? (float)vi : 0.f;
 #pragma unroll
-    for (int j = 0; j < NX; ++j) vrep[j] = rb(vi, j);
+    for (int j = 0; j < NX; ++j) vrep[j] = rb(vf, j);
 
     if (MODE == 0) {
       if (l < NX) *(float4*)(gp + l * 4) = make_float4(Kc[0], Kc[1], Kc[2], Kc[3]);
-      if (l == NX) *(float4*)(gp + 52) = make_float4(kv[0], kv[1], kv[2], kv[3]);
+      if (l == NX) *(float4*)(gp + 52) = make_float4((float)kv[0], (float)kv[1], (float)kv[2], (float)kv[3]);
       if (A.dlog && l == 0) {
         unsigned code = 0;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          const unsigned c = (fr[a] != 0.f) ? 0u : (kv[a] <= dl[a] ? 1u : 2u);
+          const unsigned c = (fr[a] != 0.0) ? 0u : (kv[a] <= dl[a] ? 1u : 2u);
           code |= c << (2 * a);
         }
         A.dlog[((size_t)b * A.K + kit) * (1 + A.Tm) + 1 + t] = (uint8_t)code;
@@ -320,23 +327,21 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, const La
         tp[12] = 0.f;
       }
       if (l < NX) *(float4*)(tp + FS + l * 4) = make_float4(Kc[0], Kc[1], Kc[2], Kc[3]);
-      // M = masked inverse of the free block (zero rows/columns on clamped controls)
-      float M[16];
+      // M = masked inverse of the free block (zero rows/columns on clamped controls), FP64
+      double M[16];
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb) {
-        float e[4];
+        double e[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) e[a] = (a == bb) ? fr[bb] : 0.f;
+        for (int a = 0; a < 4; ++a) e[a] = (a == bb) ? fr[bb] : 0.0;
         solve4(C, e);
 #pragma unroll
         for (int a = 0; a < 4; ++a) M[a * 4 + bb] = fr[a] * e[a];
       }
       if (l == NX + 1) {
-        float* mp = tp + FS + 52;
-        *(float4*)(mp) = make_float4(M[0], M[1], M[2], M[3]);
-        *(float4*)(mp + 4) = make_float4(M[4], M[5], M[6], M[7]);
-        *(float4*)(mp + 8) = make_float4(M[8], M[9], M[10], M[11]);
-        *(float4*)(mp + 12) = make_float4(M[12], M[13], M[14], M[15]);
+        double* mp = (double*)(tp + FS + 52);
+#pragma unroll
+        for (int i = 0; i < 16; i += 2) *(double2*)(mp + i) = make_double2(M[i], M[i + 1]);
       }
     }
   }
@@ -649,10 +654,10 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
   const int* s = A.ws.state + (size_t)b * SW;
   const int T = s[S_T], n = s[S_NOM], Tm = A.Tm;
   const int W = DENSE ? NPK : NZ;
-  float vrep[NX];
+  double vrep[NX];
 #pragma unroll
-  for (int i = 0; i < NX; ++i) vrep[i] = 0.f;
-  float vi = 0.f;
+  for (int i = 0; i < NX; ++i) vrep[i] = 0.0;
+  double vi = 0.0;
   // backward vector sweep: q~ = d + F^T v, k~ = -M q~_u, v = q~_x + K^T q~_u
   for (int t = T - 1; t >= 0; --t) {
     const float* tp = tail_at(A, b, t);
@@ -660,37 +665,37 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
     const float d_c = (col < NX) ? (A.gx ? A.gx[srow * NX + col] : 0.f) : A.gu[srow * NU + (col - NX)];
     const float d_0 = A.gx ? A.gx[srow * NX] : 0.f;
     const float* fc = tp + col * 16;
-    float qc = d_c;
+    double qc = (double)d_c;
 #pragma unroll
-    for (int k = 0; k < NX; ++k) qc = fmaf(fc[k], vrep[k], qc);
-    const float q0 = d_0 + vrep[0];
-    float qu[4];
+    for (int k = 0; k < NX; ++k) qc = fma((double)fc[k], vrep[k], qc);
+    const double q0 = (double)d_0 + vrep[0];
+    double qu[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) qu[a] = rb(qc, lane_of(NX + a));
-    const float* M = tp + FS + 52;
-    float kt[4];
+    for (int a = 0; a < 4; ++a) qu[a] = rb64(qc, lane_of(NX + a));
+    const double* M = (const double*)(tp + FS + 52);
+    double kt[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      float acc = 0.f;
+      double acc = 0.0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc = fmaf(M[a * 4 + c], qu[c], acc);
+      for (int c = 0; c < 4; ++c) acc = fma(M[a * 4 + c], qu[c], acc);
       kt[a] = -acc;
     }
-    if (l == 0) *(float4*)(A.ws.ktil + srow * 4) = make_float4(kt[0], kt[1], kt[2], kt[3]);
+    if (l == 0) *(float4*)(A.ws.ktil + srow * 4) = make_float4((float)kt[0], (float)kt[1], (float)kt[2], (float)kt[3]);
     vi = (l == 0) ? q0 : qc;
     if (l < NX) {
       const float4 kc = *(const float4*)(tp + FS + l * 4);
-      vi = fmaf(kc.x, qu[0], vi);
-      vi = fmaf(kc.y, qu[1], vi);
-      vi = fmaf(kc.z, qu[2], vi);
-      vi = fmaf(kc.w, qu[3], vi);
+      vi = fma((double)kc.x, qu[0], vi);
+      vi = fma((double)kc.y, qu[1], vi);
+      vi = fma((double)kc.z, qu[2], vi);
+      vi = fma((double)kc.w, qu[3], vi);
     } else {
-      vi = 0.f;
+      vi = 0.0;
     }
 #pragma unroll
-    for (int j = 0; j < NX; ++j) vrep[j] = rb(vi, j);
+    for (int j = 0; j < NX; ++j) vrep[j] = rb64(vi, j);
   }
-  if (l < NX) A.gx0[(size_t)b * NX + l] = (T > 0) ? vi : 0.f;
+  if (l < NX) A.gx0[(size_t)b * NX + l] = (T > 0) ? (float)vi : 0.f;
   mem_fence_wg();
   // forward sweep: u~ = K x~ + k~, x~' = A x~ + B u~;  dL/dc = z~, dL/dC from z~ and z*
   float xt[NX];

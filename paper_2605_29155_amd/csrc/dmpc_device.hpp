@@ -21,7 +21,7 @@ constexpr int ZS = 20;      // floats per stage in a trajectory slot: x at 0..12
 constexpr int NSLOT = 5;    // nominal + four line-search candidates
 constexpr int GS = 56;      // gains per stage: K column-major [13][4], then k[4]
 constexpr int FS = 17 * 16; // linearisation per stage: 17 columns of 13 floats, stride 16
-constexpr int TS = FS + 52 + 16; // tail per stage: F, K [13][4], M (4x4 masked inverse)
+constexpr int TS = FS + 52 + 32; // tail per stage: F, K [13][4], M (4x4 masked inverse, FP64)
 constexpr int SW = 8;       // per-instance state words
 
 // per-instance state words
@@ -62,6 +62,16 @@ __device__ __forceinline__ float rb(float v, int L) {
     default: r = __builtin_amdgcn_mov_dpp(x, 0x15F, 0xF, 0xF, false); break;
   }
   return __int_as_float(r);
+}
+
+// 64-bit row broadcast as two 32-bit DPP moves
+__device__ __forceinline__ double rb64(double v, int L) {
+  const long long x = __double_as_longlong(v);
+  const float lo = __int_as_float((int)(x & 0xffffffffLL));
+  const float hi = __int_as_float((int)(x >> 32));
+  const unsigned long long r =
+      ((unsigned long long)(unsigned)__float_as_int(rb(hi, L)) << 32) | (unsigned)__float_as_int(rb(lo, L));
+  return __longlong_as_double((long long)r);
 }
 
 // lane holding column j of F (j >= 1)
@@ -209,207 +219,204 @@ __device__ __forceinline__ void rk4_column(const Dyn& P, const float* x, const f
 }
 
 // ---------------------------------------------------------------------------
-// 4x4 Cholesky of the free block (clamped rows/cols replaced by identity),
-// FP32 with an FP64 redo when a pivot falls below the threshold
+// 4x4 control block: Cholesky of the free block (clamped rows/cols replaced by
+// identity) and the stagewise box-QP, in FP64.  The control block of the stage
+// Hessian is ill-conditioned for these costs (collective thrust has curvature
+// ~R = 1e-2 next to torque curvature ~1e3 in rotor coordinates), so it is
+// accumulated and solved in double precision.
 // ---------------------------------------------------------------------------
 
 struct Chol4 {
-  float L[10];   // L00 L10 L11 L20 L21 L22 L30 L31 L32 L33
-  float iD[4];   // 1 / L_ii
-  double Ld[10];
-  double iDd[4];
-  bool f64;
+  double L[10];  // L00 L10 L11 L20 L21 L22 L30 L31 L32 L33
+  double iD[4];  // 1 / L_ii
 };
 
-template <typename R>
-__device__ __forceinline__ bool chol4_core(const R* h, R* L, R* iD, R& dmin) {
-  R d0 = h[0];
-  R l00 = sqrt(d0 > R(0) ? d0 : R(0));
-  R i0 = R(1) / l00;
-  R l10 = h[4] * i0, l20 = h[8] * i0, l30 = h[12] * i0;
-  R d1 = h[5] - l10 * l10;
-  R l11 = sqrt(d1 > R(0) ? d1 : R(0));
-  R i1 = R(1) / l11;
-  R l21 = (h[9] - l20 * l10) * i1, l31 = (h[13] - l30 * l10) * i1;
-  R d2 = h[10] - l20 * l20 - l21 * l21;
-  R l22 = sqrt(d2 > R(0) ? d2 : R(0));
-  R i2 = R(1) / l22;
-  R l32 = (h[14] - l30 * l20 - l31 * l21) * i2;
-  R d3 = h[15] - l30 * l30 - l31 * l31 - l32 * l32;
-  R l33 = sqrt(d3 > R(0) ? d3 : R(0));
-  R i3 = R(1) / l33;
+__device__ __forceinline__ bool chol4_core(const double* h, double* L, double* iD, double& dmin) {
+  const double d0 = h[0];
+  const double l00 = sqrt(d0 > 0.0 ? d0 : 0.0), i0 = 1.0 / l00;
+  const double l10 = h[4] * i0, l20 = h[8] * i0, l30 = h[12] * i0;
+  const double d1 = h[5] - l10 * l10;
+  const double l11 = sqrt(d1 > 0.0 ? d1 : 0.0), i1 = 1.0 / l11;
+  const double l21 = (h[9] - l20 * l10) * i1, l31 = (h[13] - l30 * l10) * i1;
+  const double d2 = h[10] - l20 * l20 - l21 * l21;
+  const double l22 = sqrt(d2 > 0.0 ? d2 : 0.0), i2 = 1.0 / l22;
+  const double l32 = (h[14] - l30 * l20 - l31 * l21) * i2;
+  const double d3 = h[15] - l30 * l30 - l31 * l31 - l32 * l32;
+  const double l33 = sqrt(d3 > 0.0 ? d3 : 0.0), i3 = 1.0 / l33;
   L[0] = l00; L[1] = l10; L[2] = l11; L[3] = l20; L[4] = l21;
   L[5] = l22; L[6] = l30; L[7] = l31; L[8] = l32; L[9] = l33;
   iD[0] = i0; iD[1] = i1; iD[2] = i2; iD[3] = i3;
-  R m01 = d0 < d1 ? d0 : d1, m23 = d2 < d3 ? d2 : d3;
+  const double m01 = d0 < d1 ? d0 : d1, m23 = d2 < d3 ? d2 : d3;
   dmin = m01 < m23 ? m01 : m23;
-  return dmin > R(0);
+  return dmin > 0.0;
 }
 
-// H is the full symmetric 4x4 (row-major); fr[a] = 1 free, 0 clamped
-__device__ __forceinline__ void chol4(const float* H, const float* fr, float piv, Chol4& C, uint32_t& st) {
-  float h[16];
+// H full symmetric 4x4 (row-major); fr[a] = 1 free, 0 clamped.  A pivot below
+// piv marks the stage ill-conditioned (ST_FP64); a pivot that is not positive
+// gets a diagonal shift of 1e-6 max(1, max diag) (x10 until it factors) and
+// ST_REGULARIZED.
+__device__ __forceinline__ void chol4(const double* H, const double* fr, float piv, Chol4& C, uint32_t& st) {
+  double h[16];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-      h[a * 4 + b] = (a == b) ? (fr[a] != 0.f ? H[a * 4 + a] : 1.f) : fr[a] * fr[b] * H[a * 4 + b];
-  float dmin;
-  const bool ok = chol4_core<float>(h, C.L, C.iD, dmin);
-  C.f64 = false;
-  if (piv > 0.f ? !(dmin >= piv) : !ok) {
-    // pivot below threshold (or non-positive with the fallback disabled):
-    // refactor in FP64; a pivot that is still not positive gets a shift
-    double hd[16];
+      h[a * 4 + b] = (a == b) ? (fr[a] != 0.0 ? H[a * 4 + a] : 1.0) : fr[a] * fr[b] * H[a * 4 + b];
+  double dmin;
+  bool ok = chol4_core(h, C.L, C.iD, dmin);
+  if (piv > 0.f && !(dmin >= (double)piv)) st |= ST_FP64;
+  if (!ok) {
+    double mx = 1.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) hd[i] = (double)h[i];
-    double dm;
-    bool ok2 = chol4_core<double>(hd, C.Ld, C.iDd, dm);
-    if (piv > 0.f) st |= ST_FP64;
-    if (!ok2) {
-      double mx = 1.0;
+    for (int a = 0; a < 4; ++a) mx = h[a * 5] > mx ? h[a * 5] : mx;
+    double shift = 1e-6 * mx;
+    for (int tries = 0; tries < 8 && !ok; ++tries) {
+      double hs[16];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) mx = hd[a * 5] > mx ? hd[a * 5] : mx;
-      double shift = 1e-6 * mx;
-      for (int tries = 0; tries < 8 && !ok2; ++tries) {
+      for (int i = 0; i < 16; ++i) hs[i] = h[i];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) hd[a * 5] = (double)h[a * 5] + shift;
-        ok2 = chol4_core<double>(hd, C.Ld, C.iDd, dm);
-        shift *= 10.0;
-      }
-      st |= ST_REGULARIZED;
+      for (int a = 0; a < 4; ++a) hs[a * 5] += shift;
+      ok = chol4_core(hs, C.L, C.iD, dmin);
+      shift *= 10.0;
     }
-    C.f64 = true;
+    st |= ST_REGULARIZED;
   }
-}
-
-template <typename R>
-__device__ __forceinline__ void solve4_core(const R* L, const R* iD, R* r) {
-  R z0 = r[0] * iD[0];
-  R z1 = (r[1] - L[1] * z0) * iD[1];
-  R z2 = (r[2] - L[3] * z0 - L[4] * z1) * iD[2];
-  R z3 = (r[3] - L[6] * z0 - L[7] * z1 - L[8] * z2) * iD[3];
-  R y3 = z3 * iD[3];
-  R y2 = (z2 - L[8] * y3) * iD[2];
-  R y1 = (z1 - L[4] * y2 - L[7] * y3) * iD[1];
-  R y0 = (z0 - L[1] * y1 - L[3] * y2 - L[6] * y3) * iD[0];
-  r[0] = y0; r[1] = y1; r[2] = y2; r[3] = y3;
 }
 
 // r <- Htilde^{-1} r
-__device__ __forceinline__ void solve4(const Chol4& C, float* r) {
-  if (C.f64) {
-    double rd[4] = {(double)r[0], (double)r[1], (double)r[2], (double)r[3]};
-    solve4_core<double>(C.Ld, C.iDd, rd);
-#pragma unroll
-    for (int a = 0; a < 4; ++a) r[a] = (float)rd[a];
-  } else {
-    solve4_core<float>(C.L, C.iD, r);
-  }
+__device__ __forceinline__ void solve4(const Chol4& C, double* r) {
+  const double* L = C.L;
+  const double* iD = C.iD;
+  const double z0 = r[0] * iD[0];
+  const double z1 = (r[1] - L[1] * z0) * iD[1];
+  const double z2 = (r[2] - L[3] * z0 - L[4] * z1) * iD[2];
+  const double z3 = (r[3] - L[6] * z0 - L[7] * z1 - L[8] * z2) * iD[3];
+  const double y3 = z3 * iD[3];
+  const double y2 = (z2 - L[8] * y3) * iD[2];
+  const double y1 = (z1 - L[4] * y2 - L[7] * y3) * iD[1];
+  const double y0 = (z0 - L[1] * y1 - L[3] * y2 - L[6] * y3) * iD[0];
+  r[0] = y0; r[1] = y1; r[2] = y2; r[3] = y3;
 }
 
 __device__ __forceinline__ float clampf(float v, float lo, float hi) { return v < lo ? lo : (v > hi ? hi : v); }
+__device__ __forceinline__ double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-__device__ __forceinline__ float qp_val(const float* H, const float* q, const float* x) {
-  float f = 0.f;
+__device__ __forceinline__ double qp_val(const double* H, const double* q, const double* x) {
+  double f = 0.0;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    float s = 0.f;
+    double s = 0.0;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) s += H[a * 4 + b] * x[b];
-    f += x[a] * (0.5f * s + q[a]);
+    for (int b = 0; b < 4; ++b) s = fma(H[a * 4 + b], x[b], s);
+    f = fma(x[a], fma(0.5, s, q[a]), f);
   }
   return f;
 }
 
-// Stagewise box-QP min 1/2 d^T H d + q^T d, lo <= d <= hi, by projected Newton
-// (Tassa, Mansard & Todorov 2014): clamped set = coordinates on a bound whose
-// gradient points outward (strict), Newton step on the free block, projected
-// Armijo search.  On return x is the step, fr the free mask (1/0) and C the
-// factor of the free block for that mask.
-__device__ __forceinline__ void boxqp(const float* H, const float* q, const float* lo, const float* hi,
-                                      const float* xw, float piv, float* x, float* fr, Chol4& C, uint32_t& st) {
-  float qn = 0.f;
+__device__ __forceinline__ void qp_grad(const double* H, const double* q, const double* x, double* g) {
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    x[a] = clampf(xw[a], lo[a], hi[a]);
-    qn = fmaxf(qn, fabsf(q[a]));
+    double s = q[a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) s = fma(H[a * 4 + b], x[b], s);
+    g[a] = s;
   }
-  const float tolg = 1e-6f * (1.f + qn);
-  bool current = false;
-  bool converged = false;
-  for (int it = 0; it < 16; ++it) {
-    float g[4];
+}
+
+__device__ __forceinline__ bool qp_clamped(double x, double g, double lo, double hi) {
+  return (x <= lo && g > 0.0) || (x >= hi && g < 0.0);
+}
+
+// Stagewise box-QP min 1/2 d^T H d + q^T d, lo <= d <= hi (the bounded
+// control update of Tassa, Mansard & Todorov 2014), solved by a primal
+// active-set method on the 4-D box: from the warm start, a working set of
+// coordinates held on a bound; each iteration takes the Newton step on the free
+// face, either stops at the first bound it crosses (that coordinate joins the
+// working set) or reaches the face minimiser, where the bound with the most
+// wrongly signed multiplier is released; it stops when every multiplier has the
+// right sign.  Finite for H > 0; the minimiser is refined once on its face.
+// On return x is the step, fr the free mask (1/0) and C the factor of the free
+// block for that mask.
+__device__ __forceinline__ void boxqp(const double* H, const double* q, const double* lo, const double* hi,
+                                      const double* xw, float piv, double* x, double* fr, Chol4& C, uint32_t& st) {
+  double g[4];
+  bool W[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      float s = q[a];
+  for (int a = 0; a < 4; ++a) x[a] = clampd(xw[a], lo[a], hi[a]);
+  qp_grad(H, q, x, g);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) s += H[a * 4 + b] * x[b];
-      g[a] = s;
-    }
-    float gn = 0.f;
+  for (int a = 0; a < 4; ++a) W[a] = (lo[a] >= hi[a]) || qp_clamped(x[a], g[a], lo[a], hi[a]);
+  bool done = false;
+  for (int it = 0; it < 16 && !done; ++it) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const bool cl = (x[a] <= lo[a] && g[a] > 0.f) || (x[a] >= hi[a] && g[a] < 0.f);
-      fr[a] = cl ? 0.f : 1.f;
-      gn = fmaxf(gn, fr[a] * fabsf(g[a]));
-    }
+    for (int a = 0; a < 4; ++a) fr[a] = W[a] ? 0.0 : 1.0;
     chol4(H, fr, piv, C, st);
-    current = true;
-    if (gn <= tolg) {
-      converged = true;
-      break;
-    }
-    float d[4];
+    double d[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) d[a] = -fr[a] * g[a];
     solve4(C, d);
-    const float fx = qp_val(H, q, x);
-    float step = 1.f, xn[4];
-    bool acc = false;
-    for (int ls = 0; ls < 12; ++ls) {
-      float dec = 0.f;
+    // first bound crossed along the step, if any
+    double tau = 1.0;
+    int blk = -1;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (W[a]) continue;
+      const double v = x[a] + d[a];
+      if (d[a] < 0.0 && v < lo[a]) {
+        const double t = (lo[a] - x[a]) / d[a];
+        if (t < tau) { tau = t; blk = a; }
+      } else if (d[a] > 0.0 && v > hi[a]) {
+        const double t = (hi[a] - x[a]) / d[a];
+        if (t < tau) { tau = t; blk = a; }
+      }
+    }
+    if (blk >= 0) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        xn[a] = clampf(x[a] + step * d[a], lo[a], hi[a]);
-        dec += g[a] * (xn[a] - x[a]);
+        double v = x[a] + tau * d[a];
+        if (a == blk) {
+          v = d[a] < 0.0 ? lo[a] : hi[a];
+          W[a] = true;
+        }
+        x[a] = clampd(v, lo[a], hi[a]);
       }
-      const float fn = qp_val(H, q, xn);
-      if (fn - fx <= 0.1f * dec) {
-        acc = true;
-        break;
-      }
-      step *= 0.5f;
+      qp_grad(H, q, x, g);
+      continue;
     }
-    if (!acc) break;
-    bool moved = false;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) x[a] += d[a];
+    qp_grad(H, q, x, g);
+    // face minimiser: release the bound whose multiplier has the most wrong sign
+    int worst = -1;
+    double wv = 0.0;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      moved |= (xn[a] != x[a]);
-      x[a] = xn[a];
+      if (!W[a] || !(lo[a] < hi[a])) continue;
+      const double v = (x[a] <= lo[a]) ? -g[a] : g[a];
+      if (v > wv) { wv = v; worst = a; }
     }
-    current = false;
-    if (!moved) break;
+    if (worst < 0) {
+      done = true;
+    } else {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (a == worst) W[a] = false;
+    }
   }
-  if (!converged) {
-    // final clamped set and factor at the returned point
-    float g[4];
+  if (done) {
+    double r[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      float s = q[a];
+    for (int a = 0; a < 4; ++a) r[a] = -fr[a] * g[a];
+    solve4(C, r);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) s += H[a * 4 + b] * x[b];
-      g[a] = s;
-    }
-    float gn = 0.f;
+    for (int a = 0; a < 4; ++a) x[a] = clampd(x[a] + r[a], lo[a], hi[a]);
+  } else {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const bool cl = (x[a] <= lo[a] && g[a] > 0.f) || (x[a] >= hi[a] && g[a] < 0.f);
-      fr[a] = cl ? 0.f : 1.f;
-      gn = fmaxf(gn, fr[a] * fabsf(g[a]));
-    }
-    if (!current) chol4(H, fr, piv, C, st);
-    if (!(gn <= 1e-4f * (1.f + qn))) st |= ST_QPMAXITER;
+    for (int a = 0; a < 4; ++a) fr[a] = W[a] ? 0.0 : 1.0;
+    chol4(H, fr, piv, C, st);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) x[a] = clampd(x[a], lo[a], hi[a]);
+    st |= ST_QPMAXITER;
   }
 }
 

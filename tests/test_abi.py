@@ -1,0 +1,80 @@
+"""The C ABI library loads without a GPU, exports every entry point that
+include/dmpc.h declares, and its host-side checks return the documented codes.
+No compute call is made here."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def D():
+    import paper_2605_29155_amd as D
+    from paper_2605_29155_amd import build
+    build.build(force=False)
+    return D
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "dmpc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmpc_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("dmpc_forward", "dmpc_backward", "dmpc_workspace_bytes", "dmpc_validate", "dmpc_create"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(D):
+    L = D.lib()
+    for n in declared_functions():
+        assert hasattr(L, n), n
+
+
+def test_validate_codes(D):
+    mk = D.make_config
+    assert D.validate(mk(4096, 20, flags=D.NEED_GRAD)) == 0
+    assert D.validate(mk(0, 1)) == 0
+    assert D.validate(mk(-1, 10)) == -1
+    assert D.validate(mk(4, 0)) == -1
+    assert D.validate(mk(4, 10, max_iter=-1)) == -1
+    assert D.validate(mk(4, 2000)) == -2
+    assert D.validate(mk(4, 10, max_iter=256)) == -2
+    assert D.validate(mk(4, 10, cost_kind=7)) == -2
+    assert D.validate(mk(4, 10, flags=0x100)) == -1
+    assert D.validate(mk(4, 10, tol_du=float("nan"))) == -1
+
+
+def test_workspace_bytes(D):
+    a = D.workspace_bytes(D.make_config(4096, 20))
+    b = D.workspace_bytes(D.make_config(4096, 20, flags=D.NEED_GRAD))
+    c = D.workspace_bytes(D.make_config(4096, 20, flags=D.NEED_GRAD | D.PLAIN))
+    assert 0 < a < b < c
+    assert D.workspace_bytes(D.make_config(4, 2000)) == 0
+    # grows linearly in B
+    assert D.workspace_bytes(D.make_config(8192, 20)) > 1.9 * a
+
+
+def test_calls_without_handle_fail_cleanly(D):
+    L = D.lib()
+    cfg = D.make_config(8, 10)
+    p = D.QuadParams(0.75, 2.5e-3, 2.5e-3, 4.5e-3, 0.15, 0.01, 0.05, 9.81)
+    rc = L.dmpc_forward(None, C.byref(cfg), p, *([None] * 9), None, 0, None, None)
+    assert rc == -1
+    rc = L.dmpc_backward(None, C.byref(cfg), None, 0, None, None, None, None, None, None)
+    assert rc == -1
+    assert L.dmpc_last_launch_count(None) == -1
+    assert b"handle" in L.dmpc_last_error(None)
+
+
+def test_create_without_gpu_reports_hip_error(D):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    assert D.lib().dmpc_create(C.byref(h), 0) == -3

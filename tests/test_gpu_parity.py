@@ -87,9 +87,11 @@ def test_persistent_equals_plain():
     d = W.make(1, B=64)
     a = run_gpu(d)
     b = run_gpu(d, plain=True)
+    # same decisions; arithmetic differs only by where the linearisation is
+    # formed (in-kernel vs a separate launch), so agreement is at rounding level
     assert np.array_equal(a["dlog"], b["dlog"])
-    assert rel(a["u"], b["u"]).max() <= 1e-6
-    assert rel(a["dp"], b["dp"]).max() <= 1e-5
+    assert rel(a["u"], b["u"]).max() <= 1e-5
+    assert rel(a["dp"], b["dp"]).max() <= 1e-4
 
 
 def test_deterministic_and_lpt_invariant():
