@@ -1,0 +1,228 @@
+"""Benchmark of the batched differentiable MPC layer (forward + backward).
+
+Workload: batch 4096, horizon 20, 5 iLQR iterations, 13-state quadrotor,
+diagonal stage cost emitted per instance by a random-init 2x256 tanh MLP
+(synthetic inputs; the MLP runs once before timing and is not timed).  A step
+is one forward solve plus one backward of the whole batch, replayed from a HIP
+graph of the persistent form; the per-launch form (init, three launches per
+iteration, tail, outputs, backward) is timed beside it on the same inputs.
+
+Prints one JSON line.  The CPU baseline leg times the FP64 oracle on the host
+cores and checks the kernel's results against it on a sample (decisions
+replayed).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# canonical FLOP model per stage (1 FMA = 2 FLOP), diagonal / dense cost:
+# RK4 + nominal linearisation by the chain rule, cost gradient, Riccati with
+# box-QP, four-candidate line search; forward tail (linearise + fixed-mask
+# Riccati at the solution); adjoint sweeps; initial rollout.
+FLOP = dict(iter_stage=(27416, 30204), tail=(23478, 23478), adjoint=(1200, 2500), init=(593, 593))
+PEAK_ALU = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz, unpacked FP32 FMA = FP64 FMA rate
+PEAK_FP32_PACKED = 157.3e12
+HBM_PEAK = 8.0e12
+
+
+def flops_per_solve(T, K, dense=False):
+    i = 1 if dense else 0
+    fwd = T * (FLOP["init"][i] + K * FLOP["iter_stage"][i] + FLOP["tail"][i])
+    return fwd, T * FLOP["adjoint"][i]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("paper_2605_29155_amd/csrc/dmpc.hip", "paper_2605_29155_amd/csrc/dmpc_device.hpp", "include/dmpc.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_hash, B):
+    """HBM bytes per launch of the persistent forward kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if taken on this kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic_fwd_persistent_b4096_t20.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_hash") != kernel_hash or d.get("B") != B:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def make_inputs(dev):
+    import numpy as np
+    import torch
+
+    import workloads as W
+    d = W.make(2)
+    t = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev) for k in ("x0", "Q", "p", "lo", "hi", "grad_u")}
+    t["T"] = torch.from_numpy(d["T"]).to(dev)
+    return d, t
+
+
+def run_gpu_bench(d, t, steps, warmup):
+    import torch
+
+    import paper_2605_29155_amd as D
+    import workloads as W
+    dev = t["x0"].device
+    B, Tm, K = d["B"], d["T_max"], d["K"]
+    h = D.Handle(0)
+    params = D.quad_params(W.quad_params_f32())
+    out = {}
+    for form in ("persistent", "plain"):
+        flags = D.NEED_GRAD | (D.PLAIN if form == "plain" else D.LPT)
+        cfg = D.make_config(B, Tm, D.COST_DIAG, K, 0.0, flags)
+        ws = D.alloc_workspace(cfg, dev)
+        u = torch.empty(B, Tm, 4, device=dev)
+        x = torch.empty(B, Tm, 13, device=dev)
+        st = torch.empty(B, dtype=torch.int32, device=dev)
+        gQ, gp, gx0 = torch.empty_like(t["Q"]), torch.empty_like(t["p"]), torch.empty_like(t["x0"])
+        s = torch.cuda.Stream()
+
+        def step():
+            D.forward_raw(h, cfg, params, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], None, u, x, st, ws, None, s)
+            D.backward_raw(h, cfg, ws, t["grad_u"], None, gQ, gp, gx0, s)
+
+        with torch.cuda.stream(s):
+            step()
+        torch.cuda.synchronize()
+        launches = None
+        if form == "persistent":
+            # graph of the whole fwd+bwd step
+            D.capture_begin(h, s)
+            step()
+            g = D.capture_end(h, s)
+            run = lambda: D.graph_launch(h, g, s)  # noqa: E731
+        else:
+            D.forward_raw(h, cfg, params, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], None, u, x, st, ws, None, s)
+            launches = h.launch_count() + 1
+            run = step
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        # dominant kernel: the forward, timed by HIP events on its own stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fwd_ms = []
+        for _ in range(max(3, min(steps, 10))):
+            e0.record(s)
+            D.forward_raw(h, cfg, params, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], None, u, x, st, ws, None, s)
+            e1.record(s)
+            D.backward_raw(h, cfg, ws, t["grad_u"], None, gQ, gp, gx0, s)
+            e1.synchronize()
+            fwd_ms.append(e0.elapsed_time(e1))
+        torch.cuda.synchronize()
+        out[form] = dict(s_per_step=dt, fwd_ms=sorted(fwd_ms)[len(fwd_ms) // 2], launches=launches,
+                         u=u.cpu().numpy(), x=x.cpu().numpy(), status=st.cpu().numpy().astype("uint32"),
+                         dQ=gQ.cpu().numpy(), dp=gp.cpu().numpy(), dx0=gx0.cpu().numpy())
+        if form == "persistent":
+            D.graph_destroy(h, g)
+    return out
+
+
+def cpu_baseline_leg(d, gpu, nsample=64):
+    """Oracle on the host: time fwd + Riccati-adjoint bwd of the full batch on
+    all host cores, and check the kernel on a sample with its decisions
+    replayed (needs the decision log: one extra kernel run)."""
+    import numpy as np
+    import torch
+
+    import oracle as orc
+    import paper_2605_29155_amd as D
+    import workloads as W
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_util import oracle_replay, rel, run_gpu
+    P = orc.params_from(W.quad_params_f32())
+    nthreads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    f = orc.forward(P, d["x0"], d["Q"], d["p"], d["lo"], d["hi"], d["T"], K=d["K"], nthreads=nthreads)
+    orc.backward(P, d["x0"], d["Q"], d["p"], d["lo"], d["hi"], f["u"], f["x"], d["grad_u"], T=d["T"],
+                 nthreads=nthreads)
+    wall = time.perf_counter() - t0
+    cpu = dict(value=d["B"] / wall, unit="solves/s", cores=nthreads, kind="oracle",
+               sample="full batch B=%d T=%d K=%d, FP64 forward + Riccati-adjoint backward, %.1f s wall"
+               % (d["B"], d["T_max"], d["K"], wall))
+    # accuracy on a sample, decisions replayed
+    idx = np.arange(0, d["B"], d["B"] // nsample)[:nsample]
+    g = run_gpu(d, lpt=True)
+    o = oracle_replay(d, g, idx=idx)
+    sel = lambda a: a[idx]  # noqa: E731
+    acc = dict(sample=len(idx),
+               u_rel_max=float(rel(sel(g["u"]), o["replay"]["u"]).max()),
+               dQ_rel_max=float(rel(sel(g["dQ"]), o["bwd"]["dQ"]).max()),
+               dp_rel_max=float(rel(sel(g["dp"]), o["bwd"]["dp"]).max()),
+               dx0_rel_max=float(rel(sel(g["dx0"]), o["bwd"]["dx0"]).max()))
+    # the timed persistent run and the decision-logged run must agree exactly
+    acc["bench_run_matches_logged_run"] = bool(np.array_equal(gpu["persistent"]["u"], g["u"]))
+    torch.cuda.synchronize()
+    del D
+    return cpu, acc
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: the instances are independent and the layer has no "
+              "cross-GPU step; --gpus %d is not supported" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    dev = "cuda:0"
+    print("bench: building inputs (B=4096, T=20, MLP cost)", file=sys.stderr, flush=True)
+    d, t = make_inputs(dev)
+    print("bench: timing %d steps after %d warmup" % (a.steps, a.warmup), file=sys.stderr, flush=True)
+    res = run_gpu_bench(d, t, a.steps, a.warmup)
+    B, T, K = d["B"], d["T_max"], d["K"]
+    f_fwd, f_bwd = flops_per_solve(T, K)
+    per = res["persistent"]
+    value = B / per["s_per_step"]
+    plain_value = B / res["plain"]["s_per_step"]
+    achieved = f_fwd * B / (per["fwd_ms"] * 1e-3)
+    kh = kernel_source_hash()
+    traffic = load_traffic(kh, B)
+    line = {
+        "metric": "fwd+bwd diff-MPC solves/s @B=4096,T=20 FP32 vs plain GPU; grad rel err",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": per["s_per_step"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64acc", "data": "synthetic",
+        "config": {"workload": "diffmpc_quadrotor_B4096_T20_K5_mlpcost", "B": B, "T": T, "K": K,
+                   "cost": "diag (MLP-emitted)", "form": "persistent, hipGraph fwd+bwd"},
+        "plain": {"value": plain_value, "ms_per_step": res["plain"]["s_per_step"] * 1e3,
+                  "launches_fwd": res["plain"]["launches"], "speedup": value / plain_value},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_ALU, "traffic": traffic,
+                     "kernel": "k_fwd_persistent", "kernel_ms": per["fwd_ms"],
+                     "flop_per_solve_fwd": f_fwd, "frac_vs_fp32_packed": achieved / PEAK_FP32_PACKED},
+        "kernel_source_hash": kh,
+    }
+    if not a.no_cpu:
+        print("bench: CPU baseline leg (oracle)", file=sys.stderr, flush=True)
+        cpu, acc = cpu_baseline_leg(d, res)
+        line["cpu_baseline"] = cpu
+        line["accuracy"] = acc
+    else:
+        line["cpu_baseline"] = None
+    torch.cuda.synchronize()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
