@@ -134,6 +134,33 @@ def run_gpu_bench(d, t, steps, warmup):
     return out
 
 
+def profile_short(d, t):
+    import torch
+
+    import paper_2605_29155_amd as D
+    import workloads as W
+    dev = t["x0"].device
+    B, Tm, K = d["B"], d["T_max"], d["K"]
+    h = D.Handle(0)
+    cfg = D.make_config(B, Tm, D.COST_DIAG, K, 0.0, D.NEED_GRAD | D.LPT)
+    ws = D.alloc_workspace(cfg, dev)
+    u = torch.empty(B, Tm, 4, device=dev)
+    x = torch.empty(B, Tm, 13, device=dev)
+    st = torch.empty(B, dtype=torch.int32, device=dev)
+    gQ, gp, gx0 = torch.empty_like(t["Q"]), torch.empty_like(t["p"]), torch.empty_like(t["x0"])
+    params = D.quad_params(W.quad_params_f32())
+    for _ in range(2):
+        D.forward_raw(h, cfg, params, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], None, u, x, st, ws)
+        D.backward_raw(h, cfg, ws, t["grad_u"], None, gQ, gp, gx0)
+    torch.cuda.synchronize()
+    n = 256 << 20
+    src = torch.ones(n // 4, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print("profile-short: 2 x (fwd + bwd), then a %d-byte device copy" % n, flush=True)
+
+
 def cpu_baseline_leg(d, gpu, nsample=64):
     """Oracle on the host: time fwd + Riccati-adjoint bwd of the full batch on
     all host cores, and check the kernel on a sample with its decisions
@@ -179,6 +206,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-short", action="store_true",
+                    help="for counter collection: two direct fwd+bwd calls of the persistent form, then a "
+                         "256 MiB device copy whose FETCH_SIZE / WRITE_SIZE calibrate the HBM counters")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: the instances are independent and the layer has no "
@@ -188,6 +218,9 @@ def main():
     dev = "cuda:0"
     print("bench: building inputs (B=4096, T=20, MLP cost)", file=sys.stderr, flush=True)
     d, t = make_inputs(dev)
+    if a.profile_short:
+        profile_short(d, t)
+        return
     print("bench: timing %d steps after %d warmup" % (a.steps, a.warmup), file=sys.stderr, flush=True)
     res = run_gpu_bench(d, t, a.steps, a.warmup)
     B, T, K = d["B"], d["T_max"], d["K"]

@@ -85,8 +85,18 @@ def workspace_bytes(cfg):
     return int(lib().dmpc_workspace_bytes(C.byref(cfg)))
 
 
-def _ptr(t):
-    return None if t is None else C.c_void_p(t.data_ptr())
+def _ptr(t, dtype="float32"):
+    """Device pointer of a dense tensor; the C ABI reads plain row-major
+    buffers, so strided views and host tensors are rejected."""
+    if t is None:
+        return None
+    if t.device.type != "cuda":
+        raise DMPCError("expected a device tensor, got one on %s" % t.device)
+    if not t.is_contiguous():
+        raise DMPCError("expected a contiguous tensor of shape %s" % (tuple(t.shape),))
+    if dtype is not None and str(t.dtype) != "torch." + dtype:
+        raise DMPCError("expected %s, got %s" % (dtype, t.dtype))
+    return C.c_void_p(t.data_ptr())
 
 
 def _stream(stream=None):
@@ -132,14 +142,14 @@ def alloc_workspace(cfg, device):
 
 
 def forward_raw(h, cfg, params, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, ws, dlog=None, stream=None):
-    rc = lib().dmpc_forward(h._h, C.byref(cfg), params, _ptr(x0), _ptr(Q), _ptr(p), _ptr(u_lo), _ptr(u_hi), _ptr(T),
-                            _ptr(u_out), _ptr(x_out), _ptr(status), _ptr(ws), ws.numel() if ws is not None else 0,
-                            _ptr(dlog), _stream(stream))
+    rc = lib().dmpc_forward(h._h, C.byref(cfg), params, _ptr(x0), _ptr(Q), _ptr(p), _ptr(u_lo), _ptr(u_hi), _ptr(T, "int32"),
+                            _ptr(u_out), _ptr(x_out), _ptr(status, "int32"), _ptr(ws, "uint8"),
+                            ws.numel() if ws is not None else 0, _ptr(dlog, "uint8"), _stream(stream))
     h.check(rc, "dmpc_forward")
 
 
 def backward_raw(h, cfg, ws, grad_u, grad_x, grad_Q, grad_p, grad_x0, stream=None):
-    rc = lib().dmpc_backward(h._h, C.byref(cfg), _ptr(ws), ws.numel(), _ptr(grad_u), _ptr(grad_x), _ptr(grad_Q),
+    rc = lib().dmpc_backward(h._h, C.byref(cfg), _ptr(ws, "uint8"), ws.numel(), _ptr(grad_u), _ptr(grad_x), _ptr(grad_Q),
                              _ptr(grad_p), _ptr(grad_x0), _stream(stream))
     h.check(rc, "dmpc_backward")
 
@@ -173,6 +183,10 @@ def _make_function():
 
         @staticmethod
         def forward(ctx, x0, Q, p, u_lo, u_hi, T, layer):
+            # the C ABI reads dense row-major float32 buffers
+            x0, Q, p, u_lo, u_hi = (a.detach().float().contiguous() for a in (x0, Q, p, u_lo, u_hi))
+            if T is not None:
+                T = T.to(torch.int32).contiguous()
             B, Tm = p.shape[0], p.shape[1]
             need = any(ctx.needs_input_grad[:3])
             cfg = layer.config(B, Tm, need_grad=need)

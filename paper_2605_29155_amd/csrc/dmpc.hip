@@ -128,29 +128,73 @@ __device__ void grp_init(const KArgs& A, const Grp& G) {
   }
 }
 
+// LDS region of one instance (doubles).  V rows (stride 14), v, the F columns
+// owned by the 16 lanes (stride 14; once every lane has formed its column of
+// the stage Hessian the area holds each lane's Q_xx column instead), row 0 of
+// F^T V F by lane, the 4x4 control block with q_u, and the gain columns.  The
+// region stride (516 doubles = 4128 bytes) puts the four instances of a wave
+// on distinct LDS banks for broadcast reads.
+constexpr int L_V = 0, L_VV = 182, L_F = 198, L_QX = 198, L_Y0 = 422, L_H = 438, L_K = 462, L_REG = 516;
+
+// orders the row's LDS traffic only (outstanding global loads stay in flight)
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int N>
+__device__ __forceinline__ void lds_read(const double* p, double* v) {
+#pragma unroll
+  for (int i = 0; i + 1 < N; i += 2) {
+    const double2 w = *(const double2*)(p + i);
+    v[i] = w.x;
+    v[i + 1] = w.y;
+  }
+  if (N & 1) v[N - 1] = p[N - 1];
+}
+
+template <int N>
+__device__ __forceinline__ void lds_write(double* p, const double* v) {
+#pragma unroll
+  for (int i = 0; i + 1 < N; i += 2) *(double2*)(p + i) = make_double2(v[i], v[i + 1]);
+  if (N & 1) p[N - 1] = v[N - 1];
+}
+
 // One backward sweep t = T-1 .. 0 of the Riccati recursion (Sec. IV "Backward
 // pass with input bounds").  MODE 0: stagewise box-QP, writes K_t, k_t to the
 // gains and the pattern to the decision log.  MODE 1 (tail): the active set is
 // fixed to the controls that sit on a bound, writes F_t, K_t and the masked
 // inverse of the free block for the backward.  LIN_INLINE: A_t, B_t computed
 // here (persistent form) or read from the linearisation buffer (per-launch).
+//
+// The stage algebra accumulates in FP64: without it the Schur-complement
+// update of V loses several digits on these costs.  Lane l forms column col(l)
+// of Q = C + F^T V F; operands shared by the row (V, F columns, gains, the
+// control block) go through the instance's LDS region and are read with
+// broadcast loads.  Known columns of F are used exactly: F[:,0..2] = e_0..e_2
+// (nothing depends on position), F[:,7..9] = dt e_0..2 + e_7..9 (velocity only
+// drives position), and rows 10..12 of F[:,3..6] are zero (body rates do not
+// depend on the attitude).
 template <bool DENSE, int MODE, bool LIN_INLINE>
-__device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, const LaneDir& D, uint32_t& st) {
+__device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* L, uint32_t& st) {
   const int l = G.l, col = G.col, b = G.b, T = G.T;
-  float Vr[NX], vrep[NX];
-#pragma unroll
-  for (int i = 0; i < NX; ++i) {
-    Vr[i] = 0.f;
-    vrep[i] = 0.f;
-  }
+  const double hdt = (double)A.P.h;
+  for (int i = l; i < L_F; i += 16) L[i] = 0.0;  // V_T = 0, v_T = 0
+  lds_sync();
+  float zn[NZ];
+  if (T > 0) load_z(traj_at(A, b, n, T - 1), zn);
   for (int t = T - 1; t >= 0; --t) {
     const float* zp = traj_at(A, b, n, t);
     float zb[NZ];
-    load_z(zp, zb);
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) zb[i] = zn[i];
+    if (t > 0) load_z(traj_at(A, b, n, t - 1), zn);
     const bool has_dyn = (t + 1 < T);
     float Fc[NX];
     if (has_dyn) {
       if (LIN_INLINE) {
+        const LaneDir D = make_dir(A.P, col);
         rk4_column(A.P, zb, zb + NX, D, Fc);
       } else {
         const float* fp = lin_at(A, b, t) + col * 16;
@@ -161,158 +205,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, const La
 #pragma unroll
       for (int k = 0; k < NX; ++k) Fc[k] = 0.f;
     }
-
-    // Stage algebra, accumulated in FP64 from FP32 operands (products of two
-    // floats are exact in double): without it the Schur-complement update of V
-    // loses several digits on these costs.
-    // Y[:, col] = V F[:, col]   (V symmetric: lane k's row k is column k)
-    double Fd[NX], Yc[NX];
-#pragma unroll
-    for (int k = 0; k < NX; ++k) {
-      Fd[k] = (double)Fc[k];
-      Yc[k] = 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < NX; ++k) {
-      const double f = Fd[k];
-#pragma unroll
-      for (int i = 0; i < NX; ++i) Yc[i] = fma((double)rb(Vr[i], k), f, Yc[i]);
-    }
-    // Q[:, col] = (F^T V F)[:, col]; F[:, 0] = e_0
-    double Qc[NZ];
-    Qc[0] = Yc[0];
-#pragma unroll
-    for (int i = 1; i < NZ; ++i) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < NX; ++k) s = fma((double)rb(Fc[k], lane_of(i)), Yc[k], s);
-      Qc[i] = s;
-    }
-    // row 0 of F^T V F, gathered (only lane 0 uses it: its own column is 16)
-    double R0[NZ];
-    R0[0] = (double)Vr[0];
-#pragma unroll
-    for (int j = 1; j < NZ; ++j) R0[j] = rb64(Yc[0], lane_of(j));
-
-    // stage cost: Q += C_t, q = g + F^T v with g = C_t z + c_t
-    double qc, q0, Hd[4] = {0.0, 0.0, 0.0, 0.0};
-    {
-      const size_t srow = (size_t)b * A.Tm + t;
-      const float* prow = A.p + srow * NZ;
-      const double zb_c = (double)zp[col < NX ? col : col + 3];
-      if (!DENSE) {
-        const float* qrow = A.Q + srow * NZ;
-        const double qd_c = (double)qrow[col], qd_0 = (double)qrow[0];
-        qc = fma(qd_c, zb_c, (double)prow[col]);
-        q0 = fma(qd_0, (double)zb[0], (double)prow[0]);
-#pragma unroll
-        for (int i = 1; i < NX; ++i) Qc[i] += (i == col) ? qd_c : 0.0;
-        R0[0] += qd_0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) Hd[a] = (double)qrow[NX + a];
-      } else {
-        const float* crow = A.Q + srow * NPK;
-        double gc = (double)prow[col], g0 = (double)prow[0];
-#pragma unroll
-        for (int i = 0; i < NZ; ++i) {
-          const double cc = (double)crow[i <= col ? pidx(i, col) : pidx(col, i)];
-          const double c0 = (double)crow[i];
-          Qc[i] += cc;
-          R0[i] += c0;
-          gc = fma(cc, (double)zb[i], gc);
-          g0 = fma(c0, (double)zb[i], g0);
-        }
-        qc = gc;
-        q0 = g0;
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < NX; ++k) qc = fma(Fd[k], (double)vrep[k], qc);
-    q0 += (double)vrep[0];
-
-    // replicate the control block: H = Q_uu (upper triangle from column b), q_u
-    double H[16], qu[4];
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb) {
-#pragma unroll
-      for (int a = 0; a <= bb; ++a) {
-        const double v = rb64(Qc[NX + a], lane_of(NX + bb));
-        H[a * 4 + bb] = v;
-        H[bb * 4 + a] = v;
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      H[a * 5] += Hd[a];
-      qu[a] = rb64(qc, lane_of(NX + a));
-    }
-    double dl[4], dh[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      dl[a] = (double)G.lo[a] - (double)zb[NX + a];
-      dh[a] = (double)G.hi[a] - (double)zb[NX + a];
-    }
-
-    double kv[4] = {0.0, 0.0, 0.0, 0.0}, fr[4];
-    Chol4 C;
-    float* gp = gains_at(A, b, t);
-    if (MODE == 0) {
-      double kw[4] = {0.0, 0.0, 0.0, 0.0};
-      if (kit > 0) {
-        const float4 w = *(const float4*)(gp + 52);
-        kw[0] = w.x; kw[1] = w.y; kw[2] = w.z; kw[3] = w.w;
-      }
-      boxqp(H, qu, dl, dh, kw, A.piv, kv, fr, C, st);
-    } else {
-#pragma unroll
-      for (int a = 0; a < 4; ++a) fr[a] = (zb[NX + a] == G.lo[a] || zb[NX + a] == G.hi[a]) ? 0.0 : 1.0;
-      chol4(H, fr, A.piv, C, st);
-    }
-
-    // gain column: K[:, l] = -Qff^{-1} Q_ux[:, l] on the free rows, 0 on clamped rows
-    double Qux[4], Kd[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      Qux[a] = (l == 0) ? R0[NX + a] : Qc[NX + a];
-      Kd[a] = fr[a] * Qux[a];
-    }
-    solve4(C, Kd);
-#pragma unroll
-    for (int a = 0; a < 4; ++a) Kd[a] = -Kd[a];
-    const float Kc[4] = {(float)Kd[0], (float)Kd[1], (float)Kd[2], (float)Kd[3]};
-
-    // V row l = Q_xx[l, :] + Q_ux[:, l]^T K ;  v_l = Q_x[l] + Q_ux[:, l]^T k
-    double Vn[NX];
-#pragma unroll
-    for (int j = 0; j < NX; ++j) {
-      double s = (l == 0) ? R0[j] : Qc[j];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) s = fma(Qux[a], rb64(Kd[a], j), s);
-      Vn[j] = s;
-    }
-    double vi = (l == 0) ? q0 : qc;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) vi = fma(Qux[a], kv[a], vi);
-    const bool xl = l < NX;
-#pragma unroll
-    for (int j = 0; j < NX; ++j) Vr[j] = xl ? (float)Vn[j] : 0.f;
-    const float vf = xl ? (float)vi : 0.f;
-#pragma unroll
-    for (int j = 0; j < NX; ++j) vrep[j] = rb(vf, j);
-
-    if (MODE == 0) {
-      if (l < NX) *(float4*)(gp + l * 4) = make_float4(Kc[0], Kc[1], Kc[2], Kc[3]);
-      if (l == NX) *(float4*)(gp + 52) = make_float4((float)kv[0], (float)kv[1], (float)kv[2], (float)kv[3]);
-      if (A.dlog && l == 0) {
-        unsigned code = 0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const unsigned c = (fr[a] != 0.0) ? 0u : (kv[a] <= dl[a] ? 1u : 2u);
-          code |= c << (2 * a);
-        }
-        A.dlog[((size_t)b * A.K + kit) * (1 + A.Tm) + 1 + t] = (uint8_t)code;
-      }
-    } else {
+    if (MODE == 1) {
       float* tp = tail_at(A, b, t);
       float* fc = tp + col * 16;
       *(float4*)(fc) = make_float4(Fc[0], Fc[1], Fc[2], Fc[3]);
@@ -326,19 +219,200 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, const La
         *(float4*)(tp + 8) = make_float4(0.f, 0.f, 0.f, 0.f);
         tp[12] = 0.f;
       }
+    }
+    double Fd[NX];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) Fd[k] = (double)Fc[k];
+    lds_write<NX>(L + L_F + l * 14, Fd);
+    lds_sync();
+
+    // Y[:, col] = V F[:, col]   (V symmetric: row k is column k)
+    double Yc[NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) Yc[i] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      double vk[NX];
+      lds_read<NX>(L + L_V + k * 14, vk);
+#pragma unroll
+      for (int i = 0; i < NX; ++i) Yc[i] = fma(vk[i], Fd[k], Yc[i]);
+    }
+    // Q[:, col] = (F^T V F)[:, col]
+    double Qc[NZ];
+    Qc[0] = Yc[0];
+    Qc[1] = Yc[1];
+    Qc[2] = Yc[2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) Qc[7 + m] = fma(hdt, Yc[m], Yc[7 + m]);
+#pragma unroll
+    for (int i = 3; i < 7; ++i) {
+      double f[10];
+      lds_read<10>(L + L_F + i * 14, f);
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) s = fma(f[k], Yc[k], s);
+      Qc[i] = s;
+    }
+#pragma unroll
+    for (int i = 10; i < NZ; ++i) {
+      double f[NX];
+      lds_read<NX>(L + L_F + lane_of(i) * 14, f);
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < NX; ++k) s = fma(f[k], Yc[k], s);
+      Qc[i] = s;
+    }
+
+    // stage cost: Q += C_t, q = g + F^T v with g = C_t z + c_t
+    const size_t srow = (size_t)b * A.Tm + t;
+    const float* prow = A.p + srow * NZ;
+    double qc, g0, c00;
+    {
+      const double zb_c = (double)zp[col < NX ? col : col + 3];
+      if (!DENSE) {
+        const float* qrow = A.Q + srow * NZ;
+        const double qd_c = (double)qrow[col];
+        c00 = (double)qrow[0];
+        qc = fma(qd_c, zb_c, (double)prow[col]);
+        g0 = fma(c00, (double)zb[0], (double)prow[0]);
+#pragma unroll
+        for (int i = 1; i < NZ; ++i) Qc[i] += (i == col) ? qd_c : 0.0;
+      } else {
+        const float* crow = A.Q + srow * NPK;
+        double gc = (double)prow[col], gz = (double)prow[0];
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) {
+          const double cc = (double)crow[i <= col ? pidx(i, col) : pidx(col, i)];
+          Qc[i] += cc;
+          gc = fma(cc, (double)zb[i], gc);
+          gz = fma((double)crow[i], (double)zb[i], gz);
+        }
+        c00 = (double)crow[0];
+        qc = gc;
+        g0 = gz;
+      }
+    }
+    double vv[NX];
+    lds_read<NX>(L + L_VV, vv);
+#pragma unroll
+    for (int k = 0; k < NX; ++k) qc = fma(Fd[k], vv[k], qc);
+    const double q0 = g0 + vv[0];
+    // publish row 0 entries and the control block
+    L[L_Y0 + l] = Yc[0];
+    if (col >= NX) {
+      double h4[4] = {Qc[13], Qc[14], Qc[15], Qc[16]};
+      lds_write<4>(L + L_H + (col - NX) * 4, h4);
+      L[L_H + 16 + (col - NX)] = qc;
+    }
+    lds_sync();
+    // every lane has read the F columns: park this lane's Q_xx column there
+    lds_write<NX>(L + L_QX + l * 14, Qc);
+    double H[16], qu[4];
+    {
+      double hr[16];
+      lds_read<16>(L + L_H, hr);  // hr[b*4 + a] = Q[13+a][13+b]
+      lds_read<4>(L + L_H + 16, qu);
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int a = 0; a <= bb; ++a) {
+          H[a * 4 + bb] = hr[bb * 4 + a];
+          H[bb * 4 + a] = hr[bb * 4 + a];
+        }
+    }
+    // row 0 of Q (lane 0's x-row; its own column is 16)
+    auto R0 = [&](int j) -> double {
+      double r = (j == 0) ? L[L_V] + c00 : L[L_Y0 + lane_of(j)];
+      if (DENSE && j > 0) r += (double)A.Q[srow * NPK + j];
+      return r;
+    };
+    double dl[4], dh[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      dl[a] = (double)G.lo[a] - (double)zb[NX + a];
+      dh[a] = (double)G.hi[a] - (double)zb[NX + a];
+    }
+
+    double kv[4] = {0.0, 0.0, 0.0, 0.0}, fr[4];
+    Chol4 C;
+    float* gp = gains_at(A, b, t);
+    if (MODE == 0) {
+      double kw[4] = {0.0, 0.0, 0.0, 0.0};
+      if (kit > 0) {
+        const float4 w = *(const float4*)(gp + 64);
+        kw[0] = w.x; kw[1] = w.y; kw[2] = w.z; kw[3] = w.w;
+      }
+      boxqp(H, qu, dl, dh, kw, A.piv, kv, fr, C, st);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) fr[a] = (zb[NX + a] == G.lo[a] || zb[NX + a] == G.hi[a]) ? 0.0 : 1.0;
+      chol4(H, fr, A.piv, C, st);
+    }
+
+    // gain column: K[:, l] = -Qff^{-1} Q_ux[:, l] on the free rows, 0 on clamped rows
+    double Qux[4], Kd[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      Qux[a] = (l == 0) ? R0(NX + a) : Qc[NX + a];
+      Kd[a] = fr[a] * Qux[a];
+    }
+    solve4(C, Kd);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) Kd[a] = -Kd[a];
+    const float Kc[4] = {(float)Kd[0], (float)Kd[1], (float)Kd[2], (float)Kd[3]};
+    if (l < NX) lds_write<4>(L + L_K + l * 4, Kd);
+    lds_sync();
+
+    // V row l = Q_xx[l, :] + Q_ux[:, l]^T K ;  v_l = Q_x[l] + Q_ux[:, l]^T k
+    // (gain columns streamed from LDS, V entries written straight back)
+    if (l < NX) {
+      double vi = (l == 0) ? q0 : qc;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) vi = fma(Qux[a], kv[a], vi);
+      const double v00 = L[L_V];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        double kj[4];
+        lds_read<4>(L + L_K + j * 4, kj);
+        double s = (l == 0) ? (j == 0 ? v00 + c00 : R0(j)) : L[L_QX + l * 14 + j];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) s = fma(Qux[a], kj[a], s);
+        L[L_V + l * 14 + j] = s;
+      }
+      L[L_VV + l] = vi;
+    }
+    lds_sync();
+
+    if (MODE == 0) {
+      if (l < NX) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) gp[a * 16 + l] = Kc[a];
+      }
+      if (l == NX) *(float4*)(gp + 64) = make_float4((float)kv[0], (float)kv[1], (float)kv[2], (float)kv[3]);
+      if (A.dlog && l == 0) {
+        unsigned code = 0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const unsigned c = (fr[a] != 0.0) ? 0u : (kv[a] <= dl[a] ? 1u : 2u);
+          code |= c << (2 * a);
+        }
+        A.dlog[((size_t)b * A.K + kit) * (1 + A.Tm) + 1 + t] = (uint8_t)code;
+      }
+    } else {
+      float* tp = tail_at(A, b, t);
       if (l < NX) *(float4*)(tp + FS + l * 4) = make_float4(Kc[0], Kc[1], Kc[2], Kc[3]);
       // M = masked inverse of the free block (zero rows/columns on clamped controls), FP64
-      double M[16];
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        double e[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) e[a] = (a == bb) ? fr[bb] : 0.0;
-        solve4(C, e);
-#pragma unroll
-        for (int a = 0; a < 4; ++a) M[a * 4 + bb] = fr[a] * e[a];
-      }
       if (l == NX + 1) {
+        double M[16];
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+          double e[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) e[a] = (a == bb) ? fr[bb] : 0.0;
+          solve4(C, e);
+#pragma unroll
+          for (int a = 0; a < 4; ++a) M[a * 4 + bb] = fr[a] * e[a];
+        }
         double* mp = (double*)(tp + FS + 52);
 #pragma unroll
         for (int i = 0; i < 16; i += 2) *(double2*)(mp + i) = make_double2(M[i], M[i + 1]);
@@ -347,50 +421,77 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, const La
   }
 }
 
-// Forward pass with line search (Sec. IV): candidate a = lane & 3 rolls out
-// u = clamp(u_bar + alpha k + K (x - x_bar), lo, hi) and sums its cost.
+// Forward pass with line search (Sec. IV): the 16 lanes of an instance form
+// four quads, one per candidate alpha; lane r of a quad forms control r,
+//   u_r = clamp(u_bar_r + alpha k_r + K[r, :] (x - x_bar), lo_r, hi_r),
+// the quad shares the four controls, rolls the state out and sums the cost.
+// The next stage's nominal, gain row and cost are loaded while the current
+// stage is computed.
+template <bool DENSE>
+struct LsStage {
+  float xb[NX];
+  float ub, kr;
+  float Kr[NX];
+  float q[DENSE ? 1 : NZ];
+  float p[NZ];
+};
+
+template <bool DENSE>
+__device__ __forceinline__ void ls_load(const KArgs& A, int b, int n, int t, int r, LsStage<DENSE>& S) {
+  const float* zp = traj_at(A, b, n, t);
+  const float4 a0 = *(const float4*)(zp), a1 = *(const float4*)(zp + 4), a2 = *(const float4*)(zp + 8);
+  S.xb[0] = a0.x; S.xb[1] = a0.y; S.xb[2] = a0.z; S.xb[3] = a0.w;
+  S.xb[4] = a1.x; S.xb[5] = a1.y; S.xb[6] = a1.z; S.xb[7] = a1.w;
+  S.xb[8] = a2.x; S.xb[9] = a2.y; S.xb[10] = a2.z; S.xb[11] = a2.w;
+  S.xb[12] = zp[12];
+  S.ub = zp[16 + r];
+  const float* gp = gains_at(A, b, t);
+  S.kr = gp[64 + r];
+  const float* kp = gp + r * 16;
+  const float4 k0 = *(const float4*)(kp), k1 = *(const float4*)(kp + 4), k2 = *(const float4*)(kp + 8);
+  S.Kr[0] = k0.x; S.Kr[1] = k0.y; S.Kr[2] = k0.z; S.Kr[3] = k0.w;
+  S.Kr[4] = k1.x; S.Kr[5] = k1.y; S.Kr[6] = k1.z; S.Kr[7] = k1.w;
+  S.Kr[8] = k2.x; S.Kr[9] = k2.y; S.Kr[10] = k2.z; S.Kr[11] = k2.w;
+  S.Kr[12] = kp[12];
+  const size_t srow = (size_t)b * A.Tm + t;
+  const float* prow = A.p + srow * NZ;
+#pragma unroll
+  for (int i = 0; i < NZ; ++i) S.p[i] = prow[i];
+  if (!DENSE) {
+    const float* qrow = A.Q + srow * NZ;
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) S.q[i] = qrow[i];
+  }
+}
+
 template <bool DENSE>
 __device__ void grp_ls(const KArgs& A, const Grp& G, int n, float& Jout, float& dmax) {
-  const int a = G.l & 3, b = G.b, T = G.T;
+  const int a = G.l >> 2, r = G.l & 3, b = G.b, T = G.T;
   const float alpha = a == 0 ? 1.f : (a == 1 ? 0.5f : (a == 2 ? 0.25f : 0.1f));
   const int sc = (n + 1 + a) % NSLOT;
+  const float lo_r = A.lo[(size_t)b * NU + r], hi_r = A.hi[(size_t)b * NU + r];
   float x[NX], xn[NX];
 #pragma unroll
   for (int i = 0; i < NX; ++i) x[i] = A.x0[(size_t)b * NX + i];
   float J = 0.f, dm = 0.f;
+  LsStage<DENSE> cur, nxt;
+  if (T > 0) ls_load<DENSE>(A, b, n, 0, r, cur);
   for (int t = 0; t < T; ++t) {
-    float zb[NZ];
-    load_z(traj_at(A, b, n, t), zb);
-    const float* gp = gains_at(A, b, t);
-    float dx[NX];
+    if (t + 1 < T) ls_load<DENSE>(A, b, n, t + 1, r, nxt);
+    float ur = cur.ub + alpha * cur.kr;
 #pragma unroll
-    for (int j = 0; j < NX; ++j) dx[j] = x[j] - zb[j];
-    const float4 kk = *(const float4*)(gp + 52);
-    float u[NU] = {zb[13] + alpha * kk.x, zb[14] + alpha * kk.y, zb[15] + alpha * kk.z, zb[16] + alpha * kk.w};
-#pragma unroll
-    for (int j = 0; j < NX; ++j) {
-      const float4 kj = *(const float4*)(gp + j * 4);
-      u[0] = fmaf(kj.x, dx[j], u[0]);
-      u[1] = fmaf(kj.y, dx[j], u[1]);
-      u[2] = fmaf(kj.z, dx[j], u[2]);
-      u[3] = fmaf(kj.w, dx[j], u[3]);
-    }
-#pragma unroll
-    for (int c = 0; c < NU; ++c) {
-      u[c] = clampf(u[c], G.lo[c], G.hi[c]);
-      dm = fmaxf(dm, fabsf(u[c] - zb[NX + c]));
-    }
+    for (int j = 0; j < NX; ++j) ur = fmaf(cur.Kr[j], x[j] - cur.xb[j], ur);
+    ur = clampf(ur, lo_r, hi_r);
+    dm = fmaxf(dm, fabsf(ur - cur.ub));
     float z[NZ];
 #pragma unroll
     for (int i = 0; i < NX; ++i) z[i] = x[i];
 #pragma unroll
-    for (int c = 0; c < NU; ++c) z[NX + c] = u[c];
+    for (int c = 0; c < NU; ++c) z[NX + c] = qb(ur, c);
     const size_t srow = (size_t)b * A.Tm + t;
-    const float* prow = A.p + srow * NZ;
     if (!DENSE) {
-      const float* qrow = A.Q + srow * NZ;
 #pragma unroll
-      for (int i = 0; i < NZ; ++i) J = fmaf(fmaf(0.5f * qrow[i], z[i], prow[i]), z[i], J);
+      for (int i = 0; i < NZ; ++i) J = fmaf(fmaf(0.5f * cur.q[i], z[i], cur.p[i]), z[i], J);
     } else {
       const float* crow = A.Q + srow * NPK;
       int m = 0;
@@ -399,18 +500,27 @@ __device__ void grp_ls(const KArgs& A, const Grp& G, int n, float& Jout, float& 
         float s = 0.5f * crow[m++] * z[i];
 #pragma unroll
         for (int j = i + 1; j < NZ; ++j) s = fmaf(crow[m++], z[j], s);
-        J = fmaf(s + prow[i], z[i], J);
+        J = fmaf(s + cur.p[i], z[i], J);
       }
     }
-    if (G.l < 4) store_z(traj_at(A, b, sc, t), x, u);
+    {
+      // lane r of the quad writes floats 4r..4r+3 of the stage record, lane 0 also the controls
+      float* zo = traj_at(A, b, sc, t);
+      const float4 w = r == 0 ? make_float4(x[0], x[1], x[2], x[3])
+                     : (r == 1 ? make_float4(x[4], x[5], x[6], x[7])
+                     : (r == 2 ? make_float4(x[8], x[9], x[10], x[11]) : make_float4(x[12], 0.f, 0.f, 0.f)));
+      *(float4*)(zo + 4 * r) = w;
+      if (r == 0) *(float4*)(zo + 16) = make_float4(z[13], z[14], z[15], z[16]);
+    }
     if (t + 1 < T) {
-      rk4(A.P, x, u, xn);
+      rk4(A.P, x, z + NX, xn);
 #pragma unroll
       for (int i = 0; i < NX; ++i) x[i] = xn[i];
+      cur = nxt;
     }
   }
-  Jout = J;
-  dmax = dm;
+  Jout = J;  // all four lanes of a quad hold the same cost
+  dmax = quad_max(dm);
 }
 
 __device__ __forceinline__ float finite_or_inf(float v) {
@@ -419,9 +529,9 @@ __device__ __forceinline__ float finite_or_inf(float v) {
 
 // pick the first minimiser of the four candidate costs; returns -1 if none is finite
 __device__ __forceinline__ int ls_select(float J, float dm, float& dsel) {
-  const float c0 = finite_or_inf(rb(J, 0)), c1 = finite_or_inf(rb(J, 1)), c2 = finite_or_inf(rb(J, 2)),
-              c3 = finite_or_inf(rb(J, 3));
-  const float d0 = rb(dm, 0), d1 = rb(dm, 1), d2 = rb(dm, 2), d3 = rb(dm, 3);
+  const float c0 = finite_or_inf(rb(J, 0)), c1 = finite_or_inf(rb(J, 4)), c2 = finite_or_inf(rb(J, 8)),
+              c3 = finite_or_inf(rb(J, 12));
+  const float d0 = rb(dm, 0), d1 = rb(dm, 4), d2 = rb(dm, 8), d3 = rb(dm, 12);
   int best = -1;
   float bj = INFINITY;
   dsel = 0.f;
@@ -465,8 +575,9 @@ __device__ __forceinline__ void grp_write_state(const KArgs& A, const Grp& G, in
 
 template <bool DENSE>
 __global__ __launch_bounds__(64) void k_fwd_persistent(KArgs A) {
+  __shared__ double lds[4 * L_REG];
   const int lane = threadIdx.x, grp = lane >> 4, l = lane & 15;
-  const LaneDir D = make_dir(A.P, (l == 0) ? 16 : l);
+  double* L = lds + grp * L_REG;
   for (;;) {
     int q = 0;
     if (lane == 0) q = atomicAdd(A.ws.queue, 1);
@@ -482,7 +593,7 @@ __global__ __launch_bounds__(64) void k_fwd_persistent(KArgs A) {
       bool done = false;
       for (int k = 0; k < A.K; ++k) {
         if (done) continue;
-        grp_sweep<DENSE, 0, true>(A, G, n, k, D, st);
+        grp_sweep<DENSE, 0, true>(A, G, n, k, L, st);
         mem_fence_wg();
         float J, dm, dsel;
         grp_ls<DENSE>(A, G, n, J, dm);
@@ -502,7 +613,7 @@ __global__ __launch_bounds__(64) void k_fwd_persistent(KArgs A) {
       }
       if (A.tol > 0.f && !(st & ST_CONVERGED)) st |= ST_MAXITER;
       if (A.need_grad) {
-        grp_sweep<DENSE, 1, true>(A, G, n, 0, D, st);
+        grp_sweep<DENSE, 1, true>(A, G, n, 0, L, st);
       }
     }
     grp_outputs(A, G, n);
@@ -577,14 +688,15 @@ __global__ __launch_bounds__(64) void k_plain_lin(KArgs A, int tail) {
 
 template <bool DENSE, int MODE>
 __global__ __launch_bounds__(64) void k_plain_riccati(KArgs A) {
+  __shared__ double lds[4 * L_REG];
   const int lane = threadIdx.x, l = lane & 15;
+  double* L = lds + (lane >> 4) * L_REG;
   const Grp G = make_grp(A, blockIdx.x * 4 + (lane >> 4), l);
   if (!G.valid || G.T == 0) return;
   int* s = A.ws.state + (size_t)G.b * SW;
   if (MODE == 0 && s[S_DONE]) return;
   uint32_t st = 0;
-  LaneDir D;  // unused: F comes from the linearisation buffer
-  grp_sweep<DENSE, MODE, false>(A, G, s[S_NOM], s[S_ITERS], D, st);
+  grp_sweep<DENSE, MODE, false>(A, G, s[S_NOM], s[S_ITERS], L, st);
   mem_fence_wg();
   if (l == 0 && st) atomicOr((unsigned*)&s[S_STATUS], st);
 }

@@ -19,7 +19,7 @@ namespace dmpc_dev {
 constexpr int NX = 13, NU = 4, NZ = 17, NPK = 153;
 constexpr int ZS = 20;      // floats per stage in a trajectory slot: x at 0..12, u at 16..19
 constexpr int NSLOT = 5;    // nominal + four line-search candidates
-constexpr int GS = 56;      // gains per stage: K column-major [13][4], then k[4]
+constexpr int GS = 68;      // gains per stage: K row-major [4][16] (13 used per row), then k[4] at 64
 constexpr int FS = 17 * 16; // linearisation per stage: 17 columns of 13 floats, stride 16
 constexpr int TS = FS + 52 + 32; // tail per stage: F, K [13][4], M (4x4 masked inverse, FP64)
 constexpr int SW = 8;       // per-instance state words
@@ -72,6 +72,30 @@ __device__ __forceinline__ double rb64(double v, int L) {
   const unsigned long long r =
       ((unsigned long long)(unsigned)__float_as_int(rb(hi, L)) << 32) | (unsigned)__float_as_int(rb(lo, L));
   return __longlong_as_double((long long)r);
+}
+
+// broadcast lane Q of each 4-lane quad to the quad (Q constant after unrolling)
+__device__ __forceinline__ float qb(float v, int Q) {
+  const int x = __float_as_int(v);
+  int r;
+  switch (Q) {
+    case 0: r = __builtin_amdgcn_mov_dpp(x, 0x00, 0xF, 0xF, false); break;
+    case 1: r = __builtin_amdgcn_mov_dpp(x, 0x55, 0xF, 0xF, false); break;
+    case 2: r = __builtin_amdgcn_mov_dpp(x, 0xAA, 0xF, 0xF, false); break;
+    default: r = __builtin_amdgcn_mov_dpp(x, 0xFF, 0xF, 0xF, false); break;
+  }
+  return __int_as_float(r);
+}
+// sum / max over a 4-lane quad, identical in all four lanes
+__device__ __forceinline__ float quad_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  return v;
+}
+__device__ __forceinline__ float quad_max(float v) {
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false)));
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false)));
+  return v;
 }
 
 // lane holding column j of F (j >= 1)
@@ -231,18 +255,35 @@ struct Chol4 {
   double iD[4];  // 1 / L_ii
 };
 
+// 1/sqrt(d) and 1/d from the hardware estimates plus two Newton steps each
+// (each step doubles the correct bits), instead of the IEEE divide/sqrt
+// sequences; d > 0 for rsq.
+__device__ __forceinline__ double rsq_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double hd = 0.5 * d;
+  y = fma(y, fma(-hd * y, y, 0.5), y);
+  y = fma(y, fma(-hd * y, y, 0.5), y);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
+
 __device__ __forceinline__ bool chol4_core(const double* h, double* L, double* iD, double& dmin) {
   const double d0 = h[0];
-  const double l00 = sqrt(d0 > 0.0 ? d0 : 0.0), i0 = 1.0 / l00;
+  const double i0 = rsq_nr(d0 > 0.0 ? d0 : 1e-300), l00 = d0 * i0;
   const double l10 = h[4] * i0, l20 = h[8] * i0, l30 = h[12] * i0;
   const double d1 = h[5] - l10 * l10;
-  const double l11 = sqrt(d1 > 0.0 ? d1 : 0.0), i1 = 1.0 / l11;
+  const double i1 = rsq_nr(d1 > 0.0 ? d1 : 1e-300), l11 = d1 * i1;
   const double l21 = (h[9] - l20 * l10) * i1, l31 = (h[13] - l30 * l10) * i1;
   const double d2 = h[10] - l20 * l20 - l21 * l21;
-  const double l22 = sqrt(d2 > 0.0 ? d2 : 0.0), i2 = 1.0 / l22;
+  const double i2 = rsq_nr(d2 > 0.0 ? d2 : 1e-300), l22 = d2 * i2;
   const double l32 = (h[14] - l30 * l20 - l31 * l21) * i2;
   const double d3 = h[15] - l30 * l30 - l31 * l31 - l32 * l32;
-  const double l33 = sqrt(d3 > 0.0 ? d3 : 0.0), i3 = 1.0 / l33;
+  const double i3 = rsq_nr(d3 > 0.0 ? d3 : 1e-300), l33 = d3 * i3;
   L[0] = l00; L[1] = l10; L[2] = l11; L[3] = l20; L[4] = l21;
   L[5] = l22; L[6] = l30; L[7] = l31; L[8] = l32; L[9] = l33;
   iD[0] = i0; iD[1] = i1; iD[2] = i2; iD[3] = i3;
@@ -363,10 +404,10 @@ __device__ __forceinline__ void boxqp(const double* H, const double* q, const do
       if (W[a]) continue;
       const double v = x[a] + d[a];
       if (d[a] < 0.0 && v < lo[a]) {
-        const double t = (lo[a] - x[a]) / d[a];
+        const double t = (lo[a] - x[a]) * rcp_nr(d[a]);
         if (t < tau) { tau = t; blk = a; }
       } else if (d[a] > 0.0 && v > hi[a]) {
-        const double t = (hi[a] - x[a]) / d[a];
+        const double t = (hi[a] - x[a]) * rcp_nr(d[a]);
         if (t < tau) { tau = t; blk = a; }
       }
     }

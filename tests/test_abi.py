@@ -78,3 +78,10 @@ def test_create_without_gpu_reports_hip_error(D):
         pytest.skip("a GPU is present")
     h = C.c_void_p()
     assert D.lib().dmpc_create(C.byref(h), 0) == -3
+
+
+def test_binding_rejects_host_and_strided_tensors(D):
+    import torch
+    with pytest.raises(D.DMPCError):
+        D._ptr(torch.zeros(4, 13))
+    assert D._ptr(None) is None

@@ -1,0 +1,223 @@
+"""GPU tests of the layer as a whole: the autograd.Function with the cost MLP,
+graph capture, error codes, full-size ragged and dense workloads (sampled
+oracle parity), and central finite differences of the gradients.
+
+Tolerances: 1e-4 (u*) and 1e-3 (gradients) per-instance normwise relative
+error against the FP64 oracle replaying the kernel's decisions."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import workloads as W
+
+from gpu_util import handle, oracle_replay, rel, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+P64 = orc.params_from(W.quad_params_f32())
+
+
+def test_autograd_function_matches_raw_backward_and_oracle():
+    import torch
+
+    import paper_2605_29155_amd as D
+    d = W.make(2, B=256)
+    dev = "cuda:0"
+    layer = D.DMPCLayer(W.quad_params_f32(), max_iter=5)
+    mlp = W.CostMLP(d["T_max"], 1002, device=dev)
+    inp = torch.from_numpy(d["mlp_input"]).to(dev)
+    Q, p = mlp(inp)
+    Q.retain_grad()
+    p.retain_grad()
+    x0 = torch.from_numpy(d["x0"]).to(dev).requires_grad_(True)
+    lo, hi = torch.from_numpy(d["lo"]).to(dev), torch.from_numpy(d["hi"]).to(dev)
+    u, x, st = layer(x0, Q, p, lo, hi)
+    w = torch.from_numpy(d["w"]).to(dev)
+    loss = (u[:, 0, :] * w).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    # same numbers through the raw C ABI
+    dd = dict(d, Q=Q.detach().cpu().numpy(), p=p.detach().cpu().numpy())
+    grad_u = np.zeros((256, d["T_max"], 4), np.float32)
+    grad_u[:, 0, :] = d["w"]
+    g = run_gpu(dd, grad_u=grad_u)
+    assert np.array_equal(g["u"], u.detach().cpu().numpy())
+    assert np.array_equal(g["dQ"], Q.grad.cpu().numpy())
+    assert np.array_equal(g["dp"], p.grad.cpu().numpy())
+    assert np.array_equal(g["dx0"], x0.grad.cpu().numpy())
+    # and the oracle (decisions replayed)
+    o = oracle_replay(dd, g, grad_u=grad_u)
+    for k in ("dQ", "dp", "dx0"):
+        assert rel(g[k], o["bwd"][k]).max() <= 1e-3, k
+    assert rel(g["u"], o["replay"]["u"]).max() <= 1e-4
+    # gradients reached the MLP weights
+    assert all(prm.grad is not None and torch.isfinite(prm.grad).all() for prm in mlp.params)
+
+
+def test_graph_replay_equals_direct_launch():
+    import torch
+
+    import paper_2605_29155_amd as D
+    d = W.make(1, B=128)
+    dev = "cuda:0"
+    h = handle()
+    cfg = D.make_config(128, 20, 0, 5, 0.0, D.NEED_GRAD | D.LPT)
+    t = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev) for k in ("x0", "Q", "p", "lo", "hi", "grad_u")}
+    ws = D.alloc_workspace(cfg, dev)
+    u = torch.empty(128, 20, 4, device=dev)
+    x = torch.empty(128, 20, 13, device=dev)
+    st = torch.empty(128, dtype=torch.int32, device=dev)
+    gQ, gp, gx0 = torch.empty_like(t["Q"]), torch.empty_like(t["p"]), torch.empty_like(t["x0"])
+    par = D.quad_params(W.quad_params_f32())
+    s = torch.cuda.Stream()
+
+    def step():
+        D.forward_raw(h, cfg, par, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], None, u, x, st, ws, None, s)
+        D.backward_raw(h, cfg, ws, t["grad_u"], None, gQ, gp, gx0, s)
+
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.synchronize()
+    ref = [a.clone() for a in (u, x, st, gQ, gp, gx0)]
+    D.capture_begin(h, s)
+    step()
+    g = D.capture_end(h, s)
+    for rep in range(3):
+        for a in (u, x, gQ, gp, gx0):
+            a.fill_(float("nan"))
+        st.fill_(-1)
+        torch.cuda.synchronize()
+        D.graph_launch(h, g, s)
+        torch.cuda.synchronize()
+        for a, b in zip((u, x, st, gQ, gp, gx0), ref):
+            assert torch.equal(a, b), rep
+        # eager work between replays
+        t["x0"].add_(0.0)
+        torch.cuda.synchronize()
+    D.graph_destroy(h, g)
+
+
+def test_error_codes():
+    import torch
+
+    import paper_2605_29155_amd as D
+    h = handle()
+    dev = "cuda:0"
+    cfg = D.make_config(8, 10, 0, 5, 0.0, 0)
+    n = D.workspace_bytes(cfg)
+    x0 = torch.zeros(8, 13, device=dev)
+    Q = torch.ones(8, 10, 17, device=dev)
+    p = torch.zeros(8, 10, 17, device=dev)
+    lo, hi = torch.zeros(8, 4, device=dev), torch.full((8, 4), 8.5, device=dev)
+    u = torch.empty(8, 10, 4, device=dev)
+    st = torch.empty(8, dtype=torch.int32, device=dev)
+    par = D.quad_params(W.quad_params_f32())
+    small = D.alloc_workspace(D.make_config(1, 1), dev)
+    L = D.lib()
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ptr = lambda a: None if a is None else C.c_void_p(a.data_ptr())  # noqa: E731
+    rc = L.dmpc_forward(h._h, C.byref(cfg), par, ptr(x0), ptr(Q), ptr(p), ptr(lo), ptr(hi), None, ptr(u), None,
+                        ptr(st), ptr(small), small.numel(), None, s)
+    assert rc == -4
+    ws = D.alloc_workspace(cfg, dev)
+    rc = L.dmpc_forward(h._h, C.byref(cfg), par, None, ptr(Q), ptr(p), ptr(lo), ptr(hi), None, ptr(u), None,
+                        ptr(st), ptr(ws), n, None, s)
+    assert rc == -1
+    rc = L.dmpc_backward(h._h, C.byref(cfg), ptr(ws), n, ptr(u), None, ptr(Q), ptr(p), ptr(x0), s)
+    assert rc == -1  # forward was not run with NEED_GRAD
+    bad = D.make_config(8, 10, 0, 5, 0.0, 0, ckpt_every=10)
+    assert D.validate(bad) == -2
+    # B = 0: nothing to do, no launches
+    z = D.make_config(0, 10)
+    rc = L.dmpc_forward(h._h, C.byref(z), par, None, None, None, None, None, None, None, None, None, None, 0,
+                        None, s)
+    assert rc == 0 and h.launch_count() == 0
+    torch.cuda.synchronize()
+
+
+def test_cfg3_full_size_ragged_sampled():
+    d = W.make(3)
+    g = run_gpu(d, lpt=True)
+    idx = np.arange(0, d["B"], d["B"] // 256)[:256]
+    o = oracle_replay(d, g, idx=idx)
+    eu = rel(g["u"][idx], o["replay"]["u"])
+    eg = max(rel(g[k][idx], o["bwd"][k]).max() for k in ("dQ", "dp", "dx0"))
+    iters = (g["status"] >> 8) & 255
+    conv = (g["status"] & 1) != 0
+    print("cfg3 B=8192: u* max %.2e grads max %.2e | converged %.3f, mean iterations %.2f"
+          % (eu.max(), eg, conv.mean(), iters.mean()), flush=True)
+    assert eu.max() <= 1e-4 and eg <= 1e-3
+    assert np.all(iters <= 10) and np.all(iters >= 1)
+    # every instance either converged or hit the cap
+    assert np.all((g["status"] & 3) != 0)
+    pad = np.arange(d["T_max"])[None, :] >= d["T"][:, None]
+    assert np.all(g["u"][pad] == 0)
+
+
+def test_cfg4_full_size_dense_sampled():
+    d = W.make(4)
+    g = run_gpu(d, lpt=False, dlog=True)
+    idx = np.arange(0, d["B"], d["B"] // 32)[:32]
+    o = oracle_replay(d, g, idx=idx)
+    eu = rel(g["u"][idx], o["replay"]["u"])
+    eg = max(rel(g[k][idx], o["bwd"][k]).max() for k in ("dQ", "dp", "dx0"))
+    print("cfg4 B=16384 T=50 dense: u* max %.2e grads max %.2e" % (eu.max(), eg), flush=True)
+    assert eu.max() <= 1e-4 and eg <= 1e-3
+    assert np.all(np.isfinite(g["u"])) and np.all(np.isfinite(g["dQ"]))
+
+
+def test_central_fd_gradients_cfg2_sample():
+    """Central finite differences (h = 1e-3, FP64) of the layer's solution
+    map on 32 instances of the MLP-cost workload, run to convergence: the
+    frozen-linearisation box-LQ map at the kernel's solution is re-solved by
+    the FP64 oracle at theta +- h and the loss difference is compared with the
+    kernel's gradient (directions whose active set changes are skipped)."""
+    d = W.make(2, B=32, pu_scale=1.0)
+    g = run_gpu(d, K=60, tol=1e-6, dlog=False)
+    conv = (g["status"] & 1) != 0
+    T = d["T_max"]
+    gu = d["grad_u"].astype(np.float64)
+    checked, worst = 0, 0.0
+    rng = np.random.default_rng(0)
+    for b in np.nonzero(conv)[0][:32]:
+        xs, us = g["x"][b].astype(np.float64), g["u"][b].astype(np.float64)
+        A = np.zeros((1, T, 13, 13))
+        Bm = np.zeros((1, T, 13, 4))
+        r = np.zeros((1, T, 13))
+        for t in range(T - 1):
+            A[0, t], Bm[0, t] = orc.rk4_jac(P64, xs[t], us[t])
+            r[0, t] = orc.rk4(P64, xs[t], us[t]) - A[0, t] @ xs[t] - Bm[0, t] @ us[t]
+        base = dict(x0=d["x0"][b:b + 1].astype(np.float64), Q=d["Q"][b:b + 1].astype(np.float64),
+                    p=d["p"][b:b + 1].astype(np.float64), lo=d["lo"][b:b + 1].astype(np.float64),
+                    hi=d["hi"][b:b + 1].astype(np.float64))
+
+        def solve(pr):
+            f = orc.forward(P64, pr["x0"], pr["Q"], pr["p"], pr["lo"], pr["hi"], K=200, tol=1e-14,
+                            affine=(A, Bm, r), u_init=us[None])
+            return np.sum(f["u"] * gu[b:b + 1]), orc.active_mask(f["u"], pr["lo"], pr["hi"])
+
+        L0, m0 = solve(base)
+        dirs = [("p", (0, int(rng.integers(T)), int(rng.integers(17)))) for _ in range(4)]
+        dirs += [("x0", (0, i)) for i in (0, 4, 8)] + [("Q", (0, int(rng.integers(T)), i)) for i in (2, 9)]
+        for key, ix in dirs:
+            h = 1e-3 * (abs(base[key][ix]) if key == "Q" else 1.0)
+            vals, ok = [], True
+            for sgn in (1, -1):
+                pr = {k: v.copy() for k, v in base.items()}
+                pr[key][ix] += sgn * h
+                Lv, mv = solve(pr)
+                ok &= np.array_equal(mv, m0)
+                vals.append(Lv)
+            if not ok:
+                continue
+            fd = (vals[0] - vals[1]) / (2 * h)
+            gk = {"p": g["dp"], "x0": g["dx0"], "Q": g["dQ"]}[key][b][ix[1:]]
+            err = abs(fd - gk) / max(1.0, abs(fd))
+            worst = max(worst, err)
+            checked += 1
+    print("FD check: %d directions on %d converged instances, worst rel err %.2e" % (checked, conv.sum(), worst),
+          flush=True)
+    assert conv.sum() >= 16 and checked >= 50
+    assert worst <= 1e-3
