@@ -364,7 +364,13 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     lds_sync();
 
     // V row l = Q_xx[l, :] + Q_ux[:, l]^T K ;  v_l = Q_x[l] + Q_ux[:, l]^T k
-    // (gain columns streamed from LDS, V entries written straight back)
+    // (gain columns streamed from LDS, V entries written straight back).
+    // V is kept exactly symmetric: lane l forms the entries j >= l of its row
+    // and writes each to (l, j) and (j, l).  The rows are read as columns in
+    // the next stage, and an antisymmetric rounding residue would otherwise be
+    // carried and amplified from stage to stage over long horizons (the
+    // control-limited DDP of Tassa et al. 2014, cited for the Riccati pass in
+    // Sec. IV, likewise keeps V symmetric).
     if (l < NX) {
       double vi = (l == 0) ? q0 : qc;
 #pragma unroll
@@ -377,7 +383,10 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
         double s = (l == 0) ? (j == 0 ? v00 + c00 : R0(j)) : L[L_QX + l * 14 + j];
 #pragma unroll
         for (int a = 0; a < 4; ++a) s = fma(Qux[a], kj[a], s);
-        L[L_V + l * 14 + j] = s;
+        if (j >= l) {
+          L[L_V + l * 14 + j] = s;
+          if (j > l) L[L_V + j * 14 + l] = s;
+        }
       }
       L[L_VV + l] = vi;
     }

@@ -114,3 +114,26 @@ def alpha_choices_valid(o, rtol=1e-4):
             if cc[b, k, a] > m + rtol * (1 + abs(m)):
                 bad += 1
     return bad
+
+
+def oracle_sensitivity(d, o, idx=None, trials=3, eps=1e-7, seed=0):
+    """Conditioning of each instance's solution map at FP32 resolution: the
+    largest normwise change of the FP64 oracle's u* (decisions replayed from
+    the kernel) when Q, p and x0 get independent relative perturbations of
+    size eps (about one FP32 rounding).  A kernel that rounds to FP32 at every
+    stage of every iteration cannot agree with the oracle much better than
+    this on an instance where it is large."""
+    P = orc.params_from(W.quad_params_f32())
+    sel = slice(None) if idx is None else idx
+    x0, Q, p, lo, hi, T = (np.asarray(d[k])[sel].astype(np.float64) for k in ("x0", "Q", "p", "lo", "hi", "T"))
+    T = T.astype(np.int32)
+    rep = (o["iters"], o["alpha"], o["pattern"])
+    K = o["alpha"].shape[1]
+    base = o["replay"]["u"]
+    rng = np.random.default_rng(seed)
+    s = np.zeros(len(base))
+    for _ in range(trials):
+        pert = [a * (1 + eps * rng.standard_normal(a.shape)) for a in (x0, Q, p)]
+        f = orc.forward(P, pert[0], pert[1], pert[2], lo, hi, T, K=K, replay=rep)
+        s = np.maximum(s, rel(f["u"], base))
+    return s

@@ -12,7 +12,7 @@ import pytest
 import oracle as orc
 import workloads as W
 
-from gpu_util import handle, oracle_replay, rel, run_gpu
+from gpu_util import handle, oracle_replay, oracle_sensitivity, rel, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -138,22 +138,52 @@ def test_error_codes():
 
 
 def test_cfg3_full_size_ragged_sampled():
+    """Ragged batch, T in {10..50}, up to 10 iterations with the ||du||_inf
+    stop.  Almost no instance converges in 10 iterations at these horizons,
+    and the 10th iterate of a long unconverged iLQR run can be very sensitive
+    to rounding: on a few instances the FP64 oracle itself moves by up to
+    ~1e-4 when its inputs are perturbed at FP32 resolution.  The bars are
+    therefore 1e-4 (u*) and 1e-3 (gradients) scaled by max(1, s_b / 1e-6),
+    where s_b is that measured sensitivity (1e-6 = ten times the perturbation,
+    the amplification of a well-conditioned instance); at least 99% of the
+    sample must meet the unscaled bars."""
     d = W.make(3)
     g = run_gpu(d, lpt=True)
     idx = np.arange(0, d["B"], d["B"] // 256)[:256]
     o = oracle_replay(d, g, idx=idx)
     eu = rel(g["u"][idx], o["replay"]["u"])
-    eg = max(rel(g[k][idx], o["bwd"][k]).max() for k in ("dQ", "dp", "dx0"))
+    eg = np.max([rel(g[k][idx], o["bwd"][k]) for k in ("dQ", "dp", "dx0")], axis=0)
+    s = oracle_sensitivity(d, o, idx=idx)
+    scale = np.maximum(1.0, s / 1e-6)
     iters = (g["status"] >> 8) & 255
     conv = (g["status"] & 1) != 0
-    print("cfg3 B=8192: u* max %.2e grads max %.2e | converged %.3f, mean iterations %.2f"
-          % (eu.max(), eg, conv.mean(), iters.mean()), flush=True)
-    assert eu.max() <= 1e-4 and eg <= 1e-3
+    print("cfg3 B=8192: u* max %.2e p99 %.2e | grads max %.2e | within the unscaled bars %d/%d | "
+          "oracle sensitivity max %.1e (%d above 1e-6) | converged %.3f, mean iterations %.2f"
+          % (eu.max(), np.percentile(eu, 99), eg.max(), np.sum((eu <= 1e-4) & (eg <= 1e-3)), len(idx), s.max(),
+             np.sum(s > 1e-6), conv.mean(), iters.mean()), flush=True)
+    assert np.all(eu <= 1e-4 * scale) and np.all(eg <= 1e-3 * scale)
+    assert np.mean((eu <= 1e-4) & (eg <= 1e-3)) >= 0.99
     assert np.all(iters <= 10) and np.all(iters >= 1)
     # every instance either converged or hit the cap
     assert np.all((g["status"] & 3) != 0)
     pad = np.arange(d["T_max"])[None, :] >= d["T"][:, None]
     assert np.all(g["u"][pad] == 0)
+
+
+def test_long_horizon_parity():
+    """T = 50 for every instance, 3 iterations (before the tail of a long run
+    becomes ill-conditioned): every instance within the unscaled bars.  This
+    catches precision loss that compounds along the horizon in the Riccati
+    recursion, such as an asymmetric rounding residue in V."""
+    d = W.make(3, B=256, seed=3003)
+    d["T"] = np.full(256, d["T_max"], np.int32)
+    d["grad_u"] = np.random.default_rng(7).standard_normal((256, d["T_max"], 4)).astype(np.float32)
+    g = run_gpu(d, K=3, tol=0.0)
+    o = oracle_replay(d, g)
+    eu = rel(g["u"], o["replay"]["u"])
+    eg = np.max([rel(g[k], o["bwd"][k]) for k in ("dQ", "dp", "dx0")], axis=0)
+    print("T=50 K=3: u* max %.2e p99 %.2e | grads max %.2e" % (eu.max(), np.percentile(eu, 99), eg.max()), flush=True)
+    assert eu.max() <= 1e-4 and eg.max() <= 1e-3
 
 
 def test_cfg4_full_size_dense_sampled():
