@@ -58,7 +58,7 @@ extern "C" {
 /* return codes */
 #define DMPC_OK 0
 #define DMPC_EINVAL (-1)      /* bad sizes, NULL required pointer, lo > hi on the host side */
-#define DMPC_EUNSUPPORTED (-2) /* T_max > DMPC_T_LIMIT, unknown cost kind, checkpointing not built */
+#define DMPC_EUNSUPPORTED (-2) /* T_max > DMPC_T_LIMIT, max_iter > DMPC_K_LIMIT, unknown cost kind */
 #define DMPC_EHIP (-3)        /* HIP runtime or launch error */
 #define DMPC_EWORKSPACE (-4)  /* workspace NULL or smaller than dmpc_workspace_bytes() */
 
@@ -75,7 +75,8 @@ extern "C" {
 #define DMPC_ST_CONVERGED 0x1u   /* tol_du > 0 and ||U^k - U^{k-1}||_inf < tol_du was reached */
 #define DMPC_ST_MAXITER 0x2u     /* tol_du > 0 and the iteration cap was hit first */
 #define DMPC_ST_NONFINITE 0x4u   /* a non-finite value appeared (all line-search costs non-finite) */
-#define DMPC_ST_FP64 0x8u        /* a stage Cholesky pivot fell below fp64_pivot; redone in FP64 */
+#define DMPC_ST_FP64 0x8u        /* a stage Cholesky pivot fell below fp64_pivot (ill-conditioned stage;
+                                    the control block is always factored in FP64) */
 #define DMPC_ST_QPMAXITER 0x10u  /* a stagewise box-QP hit its iteration cap */
 #define DMPC_ST_REGULARIZED 0x20u /* a non-positive pivot remained; the block was shifted */
 #define DMPC_ST_ITERS_SHIFT 8    /* bits 8..15: iLQR iterations performed */
@@ -103,8 +104,12 @@ typedef struct {
   int32_t cost_kind;  /* DMPC_COST_DIAG or DMPC_COST_DENSE */
   int32_t max_iter;   /* iLQR iterations K (0..DMPC_K_LIMIT) */
   float tol_du;       /* <= 0: always K iterations; > 0: per-instance stop at ||dU||_inf < tol_du */
-  int32_t ckpt_every; /* 0: store every stage's factors for the backward; > 0: reserved (EUNSUPPORTED) */
-  float fp64_pivot;   /* Cholesky pivots below this are redone in FP64; <= 0 disables */
+  int32_t ckpt_every; /* 0: the forward stores every stage's factors for the backward (F_t, K_t and the
+                         masked inverse of the free control block, 1424 bytes per stage).  c > 0: it
+                         stores only V_t, v_t at t = c, 2c, ... (1584 bytes each) and dmpc_backward
+                         recomputes the factors segment by segment (twice) from those checkpoints;
+                         the gradients are the same.  Checkpointing for long horizons. */
+  float fp64_pivot;   /* pivot threshold below which a stage sets DMPC_ST_FP64; <= 0 disables */
   uint32_t flags;     /* DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT */
 } dmpc_config;
 
@@ -141,8 +146,13 @@ int dmpc_forward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, co
  * grad_p [B][T_max][17] and grad_x0 [B][13].  Uses the workspace of the
  * preceding dmpc_forward, which must have had DMPC_NEED_GRAD and the same cfg.
  * The active set is the one of the forward solution (controls equal to a
- * bound are held fixed). */
-int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, const void* workspace, size_t workspace_bytes,
+ * bound are held fixed).
+ * dyn, Q, p, u_lo, u_hi: the forward's inputs, unchanged since that call.
+ * They are read only when cfg->ckpt_every > 0 (the stage factors are then
+ * recomputed from the checkpoints) and may be NULL otherwise; a NULL one with
+ * checkpointing is DMPC_EINVAL. */
+int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* Q, const float* p,
+                  const float* u_lo, const float* u_hi, const void* workspace, size_t workspace_bytes,
                   const float* grad_u, const float* grad_x, float* grad_Q, float* grad_p, float* grad_x0,
                   void* stream);
 

@@ -56,7 +56,7 @@ def lib():
         L.dmpc_workspace_bytes.argtypes = [C.POINTER(Config)]
         L.dmpc_workspace_bytes.restype = sz
         L.dmpc_forward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 9 + [vp, sz, vp, vp]
-        L.dmpc_backward.argtypes = [vp, C.POINTER(Config), vp, sz] + [vp] * 5 + [vp]
+        L.dmpc_backward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 5 + [sz] + [vp] * 5 + [vp]
         L.dmpc_last_launch_count.argtypes = [vp]
         L.dmpc_capture_begin.argtypes = [vp, vp]
         L.dmpc_capture_end.argtypes = [vp, vp, C.POINTER(vp)]
@@ -148,9 +148,12 @@ def forward_raw(h, cfg, params, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, w
     h.check(rc, "dmpc_forward")
 
 
-def backward_raw(h, cfg, ws, grad_u, grad_x, grad_Q, grad_p, grad_x0, stream=None):
-    rc = lib().dmpc_backward(h._h, C.byref(cfg), _ptr(ws, "uint8"), ws.numel(), _ptr(grad_u), _ptr(grad_x), _ptr(grad_Q),
-                             _ptr(grad_p), _ptr(grad_x0), _stream(stream))
+def backward_raw(h, cfg, params, Q, p, u_lo, u_hi, ws, grad_u, grad_x, grad_Q, grad_p, grad_x0, stream=None):
+    """params, Q, p, u_lo, u_hi: the forward's inputs (read only with
+    checkpointing, may be None otherwise)."""
+    rc = lib().dmpc_backward(h._h, C.byref(cfg), params if params is not None else QuadParams(),
+                             _ptr(Q), _ptr(p), _ptr(u_lo), _ptr(u_hi), _ptr(ws, "uint8"), ws.numel(),
+                             _ptr(grad_u), _ptr(grad_x), _ptr(grad_Q), _ptr(grad_p), _ptr(grad_x0), _stream(stream))
     h.check(rc, "dmpc_backward")
 
 
@@ -196,6 +199,8 @@ def _make_function():
             st = torch.empty(B, device=p.device, dtype=torch.int32)
             forward_raw(layer.handle, cfg, layer.params, x0, Q, p, u_lo, u_hi, T, u, x, st, ws)
             ctx.cfg, ctx.ws, ctx.layer = cfg, ws, layer
+            # the checkpointed backward recomputes stage factors from the inputs
+            ctx.inputs = (Q, p, u_lo, u_hi) if cfg.ckpt_every > 0 else (None,) * 4
             ctx.shapes = (x0.shape, Q.shape, p.shape)
             ctx.mark_non_differentiable(st)
             return u, x, st
@@ -209,7 +214,7 @@ def _make_function():
             gQ = torch.empty(sQ, device=dev, dtype=torch.float32)
             gp = torch.empty(sp, device=dev, dtype=torch.float32)
             gx0 = torch.empty(sx0, device=dev, dtype=torch.float32)
-            backward_raw(ctx.layer.handle, ctx.cfg, ctx.ws, gu, gx, gQ, gp, gx0)
+            backward_raw(ctx.layer.handle, ctx.cfg, ctx.layer.params, *ctx.inputs, ctx.ws, gu, gx, gQ, gp, gx0)
             return gx0, gQ, gp, None, None, None, None
 
     return DMPCFunction
@@ -230,15 +235,16 @@ class DMPCLayer:
     """Callable layer: (x0, Q, p, u_lo, u_hi, T=None) -> (u*, x*, status)."""
 
     def __init__(self, params, max_iter=5, tol_du=0.0, cost_kind=COST_DIAG, plain=False, lpt=True,
-                 fp64_pivot=1e-6, device=0):
+                 fp64_pivot=1e-6, ckpt_every=0, device=0):
         self.handle = Handle(device)
         self.params = quad_params(params) if isinstance(params, dict) else params
         self.max_iter, self.tol_du, self.cost_kind = max_iter, tol_du, cost_kind
-        self.plain, self.lpt, self.fp64_pivot = plain, lpt, fp64_pivot
+        self.plain, self.lpt, self.fp64_pivot, self.ckpt_every = plain, lpt, fp64_pivot, ckpt_every
 
     def config(self, B, T_max, need_grad=True):
         flags = (NEED_GRAD if need_grad else 0) | (PLAIN if self.plain else 0) | (LPT if self.lpt else 0)
-        return make_config(B, T_max, self.cost_kind, self.max_iter, self.tol_du, flags, self.fp64_pivot)
+        return make_config(B, T_max, self.cost_kind, self.max_iter, self.tol_du, flags, self.fp64_pivot,
+                           self.ckpt_every)
 
     def __call__(self, x0, Q, p, u_lo, u_hi, T=None):
         return DMPCFunction().apply(x0, Q, p, u_lo, u_hi, T, self)

@@ -31,13 +31,16 @@ struct Ws {
   float* traj;  // [B][NSLOT][Tm][ZS]
   float* gains; // [B][Tm][GS]
   float* lin;   // [B][Tm][FS]  (per-launch form)
-  float* tail;  // [B][Tm][TS]  (stage factors for the backward)
+  float* tail;  // [B][tstride][TS]  stage factors for the backward: every stage,
+                //   or (checkpointing) one segment, recomputed by the backward
   float* ktil;  // [B][Tm][4]   (backward scratch)
+  double* ck;   // [B][nck][L_F] checkpoints of (V, v) at stages j * ckpt
 };
 
 struct KArgs {
   Dyn P;
   int B, Tm, K, need_grad, use_order, nquads;
+  int ckpt, nck, tstride;  // checkpoint interval (0 = off), checkpoints per instance, tail stages per instance
   float tol, piv;
   const float *x0, *Q, *p, *lo, *hi;
   const int* T;
@@ -67,8 +70,9 @@ __device__ __forceinline__ float* gains_at(const KArgs& A, int b, int t) {
   return A.ws.gains + ((size_t)b * A.Tm + t) * GS;
 }
 __device__ __forceinline__ float* lin_at(const KArgs& A, int b, int t) { return A.ws.lin + ((size_t)b * A.Tm + t) * FS; }
-__device__ __forceinline__ float* tail_at(const KArgs& A, int b, int t) {
-  return A.ws.tail + ((size_t)b * A.Tm + t) * TS;
+// tl: stage index within the stored range (t itself, or t - segment start)
+__device__ __forceinline__ float* tail_at(const KArgs& A, int b, int tl) {
+  return A.ws.tail + ((size_t)b * A.tstride + tl) * TS;
 }
 
 __device__ __forceinline__ int pidx(int i, int j) { return 17 * i - (i * (i - 1)) / 2 + (j - i); }
@@ -161,12 +165,16 @@ __device__ __forceinline__ void lds_write(double* p, const double* v) {
   if (N & 1) p[N - 1] = v[N - 1];
 }
 
-// One backward sweep t = T-1 .. 0 of the Riccati recursion (Sec. IV "Backward
-// pass with input bounds").  MODE 0: stagewise box-QP, writes K_t, k_t to the
-// gains and the pattern to the decision log.  MODE 1 (tail): the active set is
-// fixed to the controls that sit on a bound, writes F_t, K_t and the masked
-// inverse of the free block for the backward.  LIN_INLINE: A_t, B_t computed
-// here (persistent form) or read from the linearisation buffer (per-launch).
+// One backward sweep t = t_hi-1 .. t_lo of the Riccati recursion (Sec. IV
+// "Backward pass with input bounds"), starting from V = v = 0 or from a
+// checkpoint (vinit, the LDS image of V and v at stage t_hi).  MODE 0: stagewise
+// box-QP, writes K_t, k_t to the gains and the pattern to the decision log.
+// MODE 1 (tail): the active set is fixed to the controls that sit on a bound,
+// writes F_t, K_t and the masked inverse of the free block for the backward at
+// tail index t - tbase.  MODE 2 (tail with checkpointing): as MODE 1 but stores
+// only V and v at the stages j * ckpt, from which the backward recomputes the
+// factors segment by segment.  LIN_INLINE: A_t, B_t computed here (persistent
+// form) or read from the linearisation buffer (per-launch).
 //
 // The stage algebra accumulates in FP64: without it the Schur-complement
 // update of V loses several digits on these costs.  Lane l forms column col(l)
@@ -177,19 +185,25 @@ __device__ __forceinline__ void lds_write(double* p, const double* v) {
 // drives position), and rows 10..12 of F[:,3..6] are zero (body rates do not
 // depend on the attitude).
 template <bool DENSE, int MODE, bool LIN_INLINE>
-__device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* L, uint32_t& st) {
+__device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* L, uint32_t& st, int t_hi,
+                          int t_lo = 0, const double* vinit = nullptr, int tbase = 0) {
   const int l = G.l, col = G.col, b = G.b, T = G.T;
   const double hdt = (double)A.P.h;
-  for (int i = l; i < L_F; i += 16) L[i] = 0.0;  // V_T = 0, v_T = 0
+  for (int i = l; i < L_F; i += 16) L[i] = vinit ? vinit[i] : 0.0;  // V, v at stage t_hi (zero at T)
   lds_sync();
   float zn[NZ];
-  if (T > 0) load_z(traj_at(A, b, n, T - 1), zn);
-  for (int t = T - 1; t >= 0; --t) {
+  if (t_hi > t_lo) load_z(traj_at(A, b, n, t_hi - 1), zn);
+  for (int t = t_hi - 1; t >= t_lo; --t) {
+    if (MODE == 2 && t + 1 < T && (t + 1) % A.ckpt == 0) {
+      // V, v of stage t + 1 (complete since the last row sync): exact FP64 image
+      double* ck = A.ws.ck + ((size_t)b * A.nck + ((t + 1) / A.ckpt - 1)) * L_F;
+      for (int i = l; i < L_F; i += 16) ck[i] = L[i];
+    }
     const float* zp = traj_at(A, b, n, t);
     float zb[NZ];
 #pragma unroll
     for (int i = 0; i < NZ; ++i) zb[i] = zn[i];
-    if (t > 0) load_z(traj_at(A, b, n, t - 1), zn);
+    if (t > t_lo) load_z(traj_at(A, b, n, t - 1), zn);
     const bool has_dyn = (t + 1 < T);
     float Fc[NX];
     if (has_dyn) {
@@ -206,7 +220,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
       for (int k = 0; k < NX; ++k) Fc[k] = 0.f;
     }
     if (MODE == 1) {
-      float* tp = tail_at(A, b, t);
+      float* tp = tail_at(A, b, t - tbase);
       float* fc = tp + col * 16;
       *(float4*)(fc) = make_float4(Fc[0], Fc[1], Fc[2], Fc[3]);
       *(float4*)(fc + 4) = make_float4(Fc[4], Fc[5], Fc[6], Fc[7]);
@@ -407,8 +421,8 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
         }
         A.dlog[((size_t)b * A.K + kit) * (1 + A.Tm) + 1 + t] = (uint8_t)code;
       }
-    } else {
-      float* tp = tail_at(A, b, t);
+    } else if (MODE == 1) {
+      float* tp = tail_at(A, b, t - tbase);
       if (l < NX) *(float4*)(tp + FS + l * 4) = make_float4(Kc[0], Kc[1], Kc[2], Kc[3]);
       // M = masked inverse of the free block (zero rows/columns on clamped controls), FP64
       if (l == NX + 1) {
@@ -602,7 +616,7 @@ __global__ __launch_bounds__(64) void k_fwd_persistent(KArgs A) {
       bool done = false;
       for (int k = 0; k < A.K; ++k) {
         if (done) continue;
-        grp_sweep<DENSE, 0, true>(A, G, n, k, L, st);
+        grp_sweep<DENSE, 0, true>(A, G, n, k, L, st, G.T);
         mem_fence_wg();
         float J, dm, dsel;
         grp_ls<DENSE>(A, G, n, J, dm);
@@ -622,7 +636,8 @@ __global__ __launch_bounds__(64) void k_fwd_persistent(KArgs A) {
       }
       if (A.tol > 0.f && !(st & ST_CONVERGED)) st |= ST_MAXITER;
       if (A.need_grad) {
-        grp_sweep<DENSE, 1, true>(A, G, n, 0, L, st);
+        if (A.ckpt > 0) grp_sweep<DENSE, 2, true>(A, G, n, 0, L, st, G.T);
+        else grp_sweep<DENSE, 1, true>(A, G, n, 0, L, st, G.T);
       }
     }
     grp_outputs(A, G, n);
@@ -705,7 +720,7 @@ __global__ __launch_bounds__(64) void k_plain_riccati(KArgs A) {
   int* s = A.ws.state + (size_t)G.b * SW;
   if (MODE == 0 && s[S_DONE]) return;
   uint32_t st = 0;
-  grp_sweep<DENSE, MODE, false>(A, G, s[S_NOM], s[S_ITERS], L, st);
+  grp_sweep<DENSE, MODE, false>(A, G, s[S_NOM], s[S_ITERS], L, st, G.T);
   mem_fence_wg();
   if (l == 0 && st) atomicOr((unsigned*)&s[S_STATUS], st);
 }
@@ -766,55 +781,90 @@ __global__ __launch_bounds__(64) void k_plain_finalize(KArgs A) {
 __constant__ uint8_t c_pk_i[NPK];
 __constant__ uint8_t c_pk_j[NPK];
 
-template <bool DENSE>
+// The stage factors (F_t, K_t, masked inverse) come from the forward's tail.
+// With checkpointing (CKPT) only V, v at the stages j * ckpt were kept: the
+// horizon is cut into segments of ckpt stages and each segment's factors are
+// recomputed from its end checkpoint by the tail sweep, last segment first for
+// the backward vector sweep and first segment first for the forward sweep.
+// The checkpoint is the exact FP64 state of the forward's sweep, so the
+// recomputed factors are the ones the forward would have stored.
+template <bool DENSE, bool CKPT>
 __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
   __shared__ float zz[4][2][20];
+  __shared__ double lds[CKPT ? 4 * L_REG : 2];
   const int lane = threadIdx.x, grp = lane >> 4, l = lane & 15, col = (l == 0) ? 16 : l;
   const int b = blockIdx.x * 4 + grp;
   if (b >= A.B) return;
   const int* s = A.ws.state + (size_t)b * SW;
   const int T = s[S_T], n = s[S_NOM], Tm = A.Tm;
   const int W = DENSE ? NPK : NZ;
+  const int seg = CKPT ? A.ckpt : (T > 0 ? T : 1);
+  const int nseg = (T + seg - 1) / seg;
+  Grp G;
+  double* L = lds + (CKPT ? grp * L_REG : 0);
+  if (CKPT) {
+    G.b = b;
+    G.T = T;
+    G.l = l;
+    G.col = col;
+    G.valid = true;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      G.lo[a] = A.lo[(size_t)b * 4 + a];
+      G.hi[a] = A.hi[(size_t)b * 4 + a];
+    }
+  }
+  // factors of stages [a, e) into the tail at index t - a
+  auto recompute = [&](int a, int e) {
+    uint32_t st = 0;
+    const double* vinit = (e < T) ? A.ws.ck + ((size_t)b * A.nck + (e / seg - 1)) * L_F : nullptr;
+    grp_sweep<DENSE, 1, true>(A, G, n, 0, L, st, e, a, vinit, a);
+    mem_fence_wg();
+  };
   double vrep[NX];
 #pragma unroll
   for (int i = 0; i < NX; ++i) vrep[i] = 0.0;
   double vi = 0.0;
   // backward vector sweep: q~ = d + F^T v, k~ = -M q~_u, v = q~_x + K^T q~_u
-  for (int t = T - 1; t >= 0; --t) {
-    const float* tp = tail_at(A, b, t);
-    const size_t srow = (size_t)b * Tm + t;
-    const float d_c = (col < NX) ? (A.gx ? A.gx[srow * NX + col] : 0.f) : A.gu[srow * NU + (col - NX)];
-    const float d_0 = A.gx ? A.gx[srow * NX] : 0.f;
-    const float* fc = tp + col * 16;
-    double qc = (double)d_c;
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int a = sg * seg, e = (a + seg < T) ? a + seg : T;
+    if (CKPT) recompute(a, e);
+    for (int t = e - 1; t >= a; --t) {
+      const float* tp = tail_at(A, b, CKPT ? t - a : t);
+      const size_t srow = (size_t)b * Tm + t;
+      const float d_c = (col < NX) ? (A.gx ? A.gx[srow * NX + col] : 0.f) : A.gu[srow * NU + (col - NX)];
+      const float d_0 = A.gx ? A.gx[srow * NX] : 0.f;
+      const float* fc = tp + col * 16;
+      double qc = (double)d_c;
 #pragma unroll
-    for (int k = 0; k < NX; ++k) qc = fma((double)fc[k], vrep[k], qc);
-    const double q0 = (double)d_0 + vrep[0];
-    double qu[4];
+      for (int k = 0; k < NX; ++k) qc = fma((double)fc[k], vrep[k], qc);
+      const double q0 = (double)d_0 + vrep[0];
+      double qu[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) qu[a] = rb64(qc, lane_of(NX + a));
-    const double* M = (const double*)(tp + FS + 52);
-    double kt[4];
+      for (int a4 = 0; a4 < 4; ++a4) qu[a4] = rb64(qc, lane_of(NX + a4));
+      const double* M = (const double*)(tp + FS + 52);
+      double kt[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      double acc = 0.0;
+      for (int a4 = 0; a4 < 4; ++a4) {
+        double acc = 0.0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc = fma(M[a * 4 + c], qu[c], acc);
-      kt[a] = -acc;
+        for (int c = 0; c < 4; ++c) acc = fma(M[a4 * 4 + c], qu[c], acc);
+        kt[a4] = -acc;
+      }
+      if (l == 0) *(float4*)(A.ws.ktil + srow * 4) = make_float4((float)kt[0], (float)kt[1], (float)kt[2], (float)kt[3]);
+      vi = (l == 0) ? q0 : qc;
+      if (l < NX) {
+        const float4 kc = *(const float4*)(tp + FS + l * 4);
+        vi = fma((double)kc.x, qu[0], vi);
+        vi = fma((double)kc.y, qu[1], vi);
+        vi = fma((double)kc.z, qu[2], vi);
+        vi = fma((double)kc.w, qu[3], vi);
+      } else {
+        vi = 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < NX; ++j) vrep[j] = rb64(vi, j);
     }
-    if (l == 0) *(float4*)(A.ws.ktil + srow * 4) = make_float4((float)kt[0], (float)kt[1], (float)kt[2], (float)kt[3]);
-    vi = (l == 0) ? q0 : qc;
-    if (l < NX) {
-      const float4 kc = *(const float4*)(tp + FS + l * 4);
-      vi = fma((double)kc.x, qu[0], vi);
-      vi = fma((double)kc.y, qu[1], vi);
-      vi = fma((double)kc.z, qu[2], vi);
-      vi = fma((double)kc.w, qu[3], vi);
-    } else {
-      vi = 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < NX; ++j) vrep[j] = rb64(vi, j);
   }
   if (l < NX) A.gx0[(size_t)b * NX + l] = (T > 0) ? (float)vi : 0.f;
   mem_fence_wg();
@@ -822,10 +872,12 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
   float xt[NX];
 #pragma unroll
   for (int i = 0; i < NX; ++i) xt[i] = 0.f;
-  for (int t = 0; t < Tm; ++t) {
-    const size_t srow = (size_t)b * Tm + t;
-    if (t < T) {
-      const float* tp = tail_at(A, b, t);
+  for (int sg = 0; sg < nseg; ++sg) {
+    const int a = sg * seg, e = (a + seg < T) ? a + seg : T;
+    if (CKPT) recompute(a, e);
+    for (int t = a; t < e; ++t) {
+      const size_t srow = (size_t)b * Tm + t;
+      const float* tp = tail_at(A, b, CKPT ? t - a : t);
       const float4 kk = *(const float4*)(A.ws.ktil + srow * 4);
       float ut[4] = {kk.x, kk.y, kk.z, kk.w};
 #pragma unroll
@@ -842,16 +894,16 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
         float* zt = zz[grp][0];
         float* zr = zz[grp][1];
         for (int i = 0; i < NX; ++i) zt[i] = xt[i];
-        for (int a = 0; a < NU; ++a) zt[NX + a] = ut[a];
+        for (int a4 = 0; a4 < NU; ++a4) zt[NX + a4] = ut[a4];
         for (int i = 0; i < NZ; ++i) zr[i] = zs[i];
       }
       mem_fence_wg();
       __builtin_amdgcn_wave_barrier();
       const float* zt = zz[grp][0];
       const float* zr = zz[grp][1];
-      for (int e = l; e < NZ; e += 16) A.gp[srow * NZ + e] = zt[e];
+      for (int ee = l; ee < NZ; ee += 16) A.gp[srow * NZ + ee] = zt[ee];
       if (!DENSE) {
-        for (int e = l; e < NZ; e += 16) A.gQ[srow * NZ + e] = zt[e] * zr[e];
+        for (int ee = l; ee < NZ; ee += 16) A.gQ[srow * NZ + ee] = zt[ee] * zr[ee];
       } else {
         for (int m = l; m < NPK; m += 16) {
           const int i = c_pk_i[m], j = c_pk_j[m];
@@ -867,15 +919,17 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
 #pragma unroll
           for (int c = 0; c < NX; ++c) xi = fmaf(tp[c * 16 + l], xt[c], xi);
 #pragma unroll
-          for (int a = 0; a < NU; ++a) xi = fmaf(tp[(NX + a) * 16 + l], ut[a], xi);
+          for (int a4 = 0; a4 < NU; ++a4) xi = fmaf(tp[(NX + a4) * 16 + l], ut[a4], xi);
         }
 #pragma unroll
         for (int j = 0; j < NX; ++j) xt[j] = rb(xi, j);
       }
-    } else {
-      for (int e = l; e < NZ; e += 16) A.gp[srow * NZ + e] = 0.f;
-      for (int m = l; m < W; m += 16) A.gQ[srow * W + m] = 0.f;
     }
+  }
+  for (int t = T; t < Tm; ++t) {
+    const size_t srow = (size_t)b * Tm + t;
+    for (int ee = l; ee < NZ; ee += 16) A.gp[srow * NZ + ee] = 0.f;
+    for (int m = l; m < W; m += 16) A.gQ[srow * W + m] = 0.f;
   }
 }
 
@@ -884,7 +938,8 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
 // ---------------------------------------------------------------------------
 
 struct Layout {
-  size_t state, queue, order, traj, gains, lin, tail, ktil, total;
+  size_t state, queue, order, traj, gains, lin, tail, ktil, ck, total;
+  int tstride, nck;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -894,7 +949,7 @@ int check_cfg(const dmpc_config* c) {
   if (c->B < 0 || c->T_max < 1 || c->max_iter < 0) return DMPC_EINVAL;
   if (c->T_max > DMPC_T_LIMIT || c->max_iter > DMPC_K_LIMIT) return DMPC_EUNSUPPORTED;
   if (c->cost_kind != DMPC_COST_DIAG && c->cost_kind != DMPC_COST_DENSE) return DMPC_EUNSUPPORTED;
-  if (c->ckpt_every != 0) return DMPC_EUNSUPPORTED;
+  if (c->ckpt_every < 0) return DMPC_EINVAL;
   if (!(c->tol_du == c->tol_du) || !(c->fp64_pivot == c->fp64_pivot)) return DMPC_EINVAL;
   if (c->flags & ~(DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT)) return DMPC_EINVAL;
   return DMPC_OK;
@@ -916,8 +971,14 @@ Layout make_layout(const dmpc_config* c) {
   L.gains = take(B * Tm * GS * sizeof(float));
   L.lin = (c->flags & DMPC_PLAIN) ? take(B * Tm * FS * sizeof(float)) : take(0);
   const bool g = (c->flags & DMPC_NEED_GRAD) != 0;
-  L.tail = take(g ? B * Tm * TS * sizeof(float) : 0);
+  const int ck = c->ckpt_every;
+  // checkpointing keeps one segment of factors per instance (the backward's
+  // recompute buffer) and (V, v) at the stages j * ck < T_max
+  L.tstride = (ck > 0) ? std::min(ck, c->T_max) : c->T_max;
+  L.nck = (ck > 0) ? (c->T_max - 1) / ck : 0;
+  L.tail = take(g ? B * (size_t)L.tstride * TS * sizeof(float) : 0);
   L.ktil = take(g ? B * Tm * 4 * sizeof(float) : 0);
+  L.ck = take(g ? B * (size_t)L.nck * L_F * sizeof(double) : 0);
   L.total = off;
   return L;
 }
@@ -1006,6 +1067,10 @@ KArgs base_args(const dmpc_config* c, void* workspace) {
   A.ws.lin = (float*)(w + L.lin);
   A.ws.tail = (float*)(w + L.tail);
   A.ws.ktil = (float*)(w + L.ktil);
+  A.ws.ck = (double*)(w + L.ck);
+  A.ckpt = c->ckpt_every;
+  A.nck = L.nck;
+  A.tstride = L.tstride;
   return A;
 }
 
@@ -1112,8 +1177,13 @@ int dmpc_forward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, co
     }
     if (A.need_grad) {
       k_plain_lin<<<lin_grid, 64, 0, s>>>(A, 1);
-      if (dense) k_plain_riccati<true, 1><<<nq, 64, 0, s>>>(A);
-      else k_plain_riccati<false, 1><<<nq, 64, 0, s>>>(A);
+      if (A.ckpt > 0) {
+        if (dense) k_plain_riccati<true, 2><<<nq, 64, 0, s>>>(A);
+        else k_plain_riccati<false, 2><<<nq, 64, 0, s>>>(A);
+      } else {
+        if (dense) k_plain_riccati<true, 1><<<nq, 64, 0, s>>>(A);
+        else k_plain_riccati<false, 1><<<nq, 64, 0, s>>>(A);
+      }
       launches += 2;
     }
     k_plain_finalize<<<nq, 64, 0, s>>>(A);
@@ -1136,7 +1206,8 @@ int dmpc_forward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, co
   return hip_check(h, hipGetLastError(), "kernel launch");
 }
 
-int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, const void* workspace, size_t workspace_bytes,
+int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* Q, const float* p,
+                  const float* u_lo, const float* u_hi, const void* workspace, size_t workspace_bytes,
                   const float* grad_u, const float* grad_x, float* grad_Q, float* grad_p, float* grad_x0,
                   void* stream) {
   if (!h) return fail(nullptr, DMPC_EINVAL, "NULL handle");
@@ -1146,6 +1217,11 @@ int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, const void* workspace, 
   if (!(cfg->flags & DMPC_NEED_GRAD)) return fail(h, DMPC_EINVAL, "backward needs a forward run with DMPC_NEED_GRAD");
   if (cfg->B == 0) return DMPC_OK;
   if (!grad_u || !grad_Q || !grad_p || !grad_x0) return fail(h, DMPC_EINVAL, "NULL required pointer");
+  const bool ckpt = cfg->ckpt_every > 0;
+  if (ckpt && (!Q || !p || !u_lo || !u_hi))
+    return fail(h, DMPC_EINVAL, "checkpointed backward needs the forward's Q, p, u_lo, u_hi");
+  if (ckpt && (!(dyn.mass > 0.f) || !(dyn.Jxx > 0.f) || !(dyn.Jyy > 0.f) || !(dyn.Jzz > 0.f) || !(dyn.dt > 0.f)))
+    return fail(h, DMPC_EINVAL, "non-positive mass, inertia or step");
   const Layout L = make_layout(cfg);
   if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace & 255))
     return fail(h, DMPC_EWORKSPACE, "workspace missing, misaligned or smaller than dmpc_workspace_bytes()");
@@ -1158,8 +1234,19 @@ int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, const void* workspace, 
   A.gp = grad_p;
   A.gx0 = grad_x0;
   hipStream_t s = (hipStream_t)stream;
-  if (cfg->cost_kind == DMPC_COST_DENSE) k_bwd<true><<<A.nquads, 64, 0, s>>>(A);
-  else k_bwd<false><<<A.nquads, 64, 0, s>>>(A);
+  const bool dense = cfg->cost_kind == DMPC_COST_DENSE;
+  if (ckpt) {
+    A.P = make_dyn(dyn);
+    A.Q = Q;
+    A.p = p;
+    A.lo = u_lo;
+    A.hi = u_hi;
+    if (dense) k_bwd<true, true><<<A.nquads, 64, 0, s>>>(A);
+    else k_bwd<false, true><<<A.nquads, 64, 0, s>>>(A);
+  } else {
+    if (dense) k_bwd<true, false><<<A.nquads, 64, 0, s>>>(A);
+    else k_bwd<false, false><<<A.nquads, 64, 0, s>>>(A);
+  }
   h->last_launches = 1;
   return hip_check(h, hipGetLastError(), "kernel launch");
 }

@@ -26,7 +26,7 @@ def rel(a, b, axis_from=1):
 
 
 def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=True, grad_u=None, grad_x=None,
-            fp64_pivot=1e-6):
+            fp64_pivot=1e-6, ckpt=0):
     import torch
 
     import paper_2605_29155_amd as D
@@ -36,7 +36,7 @@ def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=Tru
     K = d["K"] if K is None else K
     tol = d["tol"] if tol is None else tol
     flags = (D.NEED_GRAD if need_grad else 0) | (D.PLAIN if plain else 0) | (D.LPT if lpt else 0)
-    cfg = D.make_config(B, Tm, d["cost_kind"], K, tol, flags, fp64_pivot)
+    cfg = D.make_config(B, Tm, d["cost_kind"], K, tol, flags, fp64_pivot, ckpt)
     t = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev) for k in ("x0", "Q", "p", "lo", "hi")}
     Tt = torch.from_numpy(d["T"].astype(np.int32)).to(dev)
     ws = D.alloc_workspace(cfg, dev)
@@ -44,8 +44,8 @@ def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=Tru
     x = torch.full((B, Tm, 13), float("nan"), device=dev)
     st = torch.zeros(B, dtype=torch.int32, device=dev)
     dl = torch.zeros((B, max(K, 1), 1 + Tm), dtype=torch.uint8, device=dev) if dlog else None
-    D.forward_raw(h, cfg, D.quad_params(W.quad_params_f32()), t["x0"], t["Q"], t["p"], t["lo"], t["hi"], Tt, u, x,
-                  st, ws, dl)
+    par = D.quad_params(W.quad_params_f32())
+    D.forward_raw(h, cfg, par, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], Tt, u, x, st, ws, dl)
     out = dict(launches_fwd=h.launch_count())
     if need_grad:
         gu = torch.from_numpy(np.ascontiguousarray(d["grad_u"] if grad_u is None else grad_u)).to(dev)
@@ -53,7 +53,7 @@ def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=Tru
         gQ = torch.full_like(t["Q"], float("nan"))
         gp = torch.full_like(t["p"], float("nan"))
         gx0 = torch.full_like(t["x0"], float("nan"))
-        D.backward_raw(h, cfg, ws, gu, gx, gQ, gp, gx0)
+        D.backward_raw(h, cfg, par, t["Q"], t["p"], t["lo"], t["hi"], ws, gu, gx, gQ, gp, gx0)
         out["launches_bwd"] = h.launch_count()
     torch.cuda.synchronize()
     out.update(u=u.cpu().numpy(), x=x.cpu().numpy(), status=st.cpu().numpy().astype(np.uint32), K=K)

@@ -66,7 +66,8 @@ def test_calls_without_handle_fail_cleanly(D):
     p = D.QuadParams(0.75, 2.5e-3, 2.5e-3, 4.5e-3, 0.15, 0.01, 0.05, 9.81)
     rc = L.dmpc_forward(None, C.byref(cfg), p, *([None] * 9), None, 0, None, None)
     assert rc == -1
-    rc = L.dmpc_backward(None, C.byref(cfg), None, 0, None, None, None, None, None, None)
+    rc = L.dmpc_backward(None, C.byref(cfg), D.QuadParams(), None, None, None, None, None, 0, None, None, None, None,
+                         None, None)
     assert rc == -1
     assert L.dmpc_last_launch_count(None) == -1
     assert b"handle" in L.dmpc_last_error(None)
@@ -85,3 +86,12 @@ def test_binding_rejects_host_and_strided_tensors(D):
     with pytest.raises(D.DMPCError):
         D._ptr(torch.zeros(4, 13))
     assert D._ptr(None) is None
+
+
+def test_checkpoint_workspace(D):
+    full = D.workspace_bytes(D.make_config(16384, 50, D.COST_DENSE, flags=D.NEED_GRAD))
+    ck = D.workspace_bytes(D.make_config(16384, 50, D.COST_DENSE, flags=D.NEED_GRAD, ckpt_every=10))
+    assert D.validate(D.make_config(16384, 50, D.COST_DENSE, flags=D.NEED_GRAD, ckpt_every=10)) == 0
+    assert D.validate(D.make_config(4, 10, ckpt_every=-1)) == -1
+    # stage factors: 1424 bytes per stage; checkpoints: 10 stages of factors + 4 x 1584 bytes
+    assert full - ck >= 16384 * (50 - 10) * 1424 - 16384 * 4 * 1584

@@ -75,7 +75,7 @@ def test_graph_replay_equals_direct_launch():
 
     def step():
         D.forward_raw(h, cfg, par, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], None, u, x, st, ws, None, s)
-        D.backward_raw(h, cfg, ws, t["grad_u"], None, gQ, gp, gx0, s)
+        D.backward_raw(h, cfg, par, None, None, None, None, ws, t["grad_u"], None, gQ, gp, gx0, s)
 
     with torch.cuda.stream(s):
         step()
@@ -125,10 +125,17 @@ def test_error_codes():
     rc = L.dmpc_forward(h._h, C.byref(cfg), par, None, ptr(Q), ptr(p), ptr(lo), ptr(hi), None, ptr(u), None,
                         ptr(st), ptr(ws), n, None, s)
     assert rc == -1
-    rc = L.dmpc_backward(h._h, C.byref(cfg), ptr(ws), n, ptr(u), None, ptr(Q), ptr(p), ptr(x0), s)
+    rc = L.dmpc_backward(h._h, C.byref(cfg), par, None, None, None, None, ptr(ws), n, ptr(u), None, ptr(Q), ptr(p),
+                         ptr(x0), s)
     assert rc == -1  # forward was not run with NEED_GRAD
-    bad = D.make_config(8, 10, 0, 5, 0.0, 0, ckpt_every=10)
-    assert D.validate(bad) == -2
+    # a checkpointed backward needs the forward's cost and bounds
+    cc = D.make_config(8, 10, 0, 5, 0.0, D.NEED_GRAD, ckpt_every=4)
+    wc = D.alloc_workspace(cc, dev)
+    gu = torch.zeros(8, 10, 4, device=dev)
+    rc = L.dmpc_backward(h._h, C.byref(cc), par, None, ptr(p), ptr(lo), ptr(hi), ptr(wc), wc.numel(), ptr(gu), None,
+                         ptr(Q), ptr(p), ptr(x0), s)
+    assert rc == -1
+    assert D.validate(D.make_config(8, 10, 0, 5, 0.0, 0, ckpt_every=-1)) == -1
     # B = 0: nothing to do, no launches
     z = D.make_config(0, 10)
     rc = L.dmpc_forward(h._h, C.byref(z), par, None, None, None, None, None, None, None, None, None, None, 0,
@@ -188,7 +195,8 @@ def test_long_horizon_parity():
 
 def test_cfg4_full_size_dense_sampled():
     d = W.make(4)
-    g = run_gpu(d, lpt=False, dlog=True)
+    assert d["ckpt"] == 10
+    g = run_gpu(d, lpt=False, dlog=True, ckpt=d["ckpt"])
     idx = np.arange(0, d["B"], d["B"] // 32)[:32]
     o = oracle_replay(d, g, idx=idx)
     eu = rel(g["u"][idx], o["replay"]["u"])
@@ -251,3 +259,31 @@ def test_central_fd_gradients_cfg2_sample():
           flush=True)
     assert conv.sum() >= 16 and checked >= 50
     assert worst <= 1e-3
+
+
+@pytest.mark.parametrize("cfg_id,B,plain", [(3, 64, False), (3, 64, True), (4, 32, False)],
+                         ids=["ragged-persistent", "ragged-plain", "dense-persistent"])
+def test_checkpointed_backward_equals_stored_factors(cfg_id, B, plain):
+    """The checkpointed backward recomputes each segment's factors from the
+    exact FP64 (V, v) the forward kept with the same sweep, so in the
+    persistent form its gradients are bitwise those of the stored-factor
+    backward; segment lengths 1, 7, 10 and one longer than the horizon,
+    ragged horizons including 0 and 1."""
+    d = W.make(cfg_id, B=B, T=50, seed=4000 + cfg_id)
+    if cfg_id == 3:
+        d["T"][:4] = [0, 1, 10, 50]
+        pad = np.arange(d["T_max"])[None, :] >= d["T"][:, None]
+        d["grad_u"][pad] = 0
+    ref = run_gpu(d, plain=plain, dlog=False)
+    for c in (10, 7, 1, 64):
+        g = run_gpu(d, plain=plain, dlog=False, ckpt=c)
+        assert np.array_equal(g["u"], ref["u"]) and np.array_equal(g["status"], ref["status"]), c
+        diffs = {k: rel(g[k], ref[k]).max() for k in ("dQ", "dp", "dx0")}
+        same = all(np.array_equal(g[k], ref[k]) for k in ("dQ", "dp", "dx0"))
+        print("ckpt %2d: bitwise equal %s, max rel diff %s" % (c, same, diffs), flush=True)
+        if plain:
+            # the per-launch forward stored F from its separate linearisation
+            # launch; the recompute linearises in the sweep (FP32 rounding differs)
+            assert max(diffs.values()) <= 1e-5, (c, diffs)
+        else:
+            assert same, (c, diffs)
