@@ -70,6 +70,9 @@ extern "C" {
 #define DMPC_NEED_GRAD 0x1u /* forward also factors the stages at (x*, u*) for dmpc_backward */
 #define DMPC_PLAIN 0x2u     /* per-launch form: init, three launches per iteration, tail, outputs */
 #define DMPC_LPT 0x4u       /* persistent form: process instances by decreasing T_b */
+#define DMPC_TUNED 0x8u     /* use the launch choice dmpc_autotune (or dmpc_set_tuned) stored on the
+                               handle for this problem shape, instead of DMPC_PLAIN / DMPC_LPT; without
+                               a stored choice the flags decide */
 
 /* per-instance status word */
 #define DMPC_ST_CONVERGED 0x1u   /* tol_du > 0 and ||U^k - U^{k-1}||_inf < tol_du was reached */
@@ -110,8 +113,22 @@ typedef struct {
                          recomputes the factors segment by segment (twice) from those checkpoints;
                          the gradients are the same.  Checkpointing for long horizons. */
   float fp64_pivot;   /* pivot threshold below which a stage sets DMPC_ST_FP64; <= 0 disables */
-  uint32_t flags;     /* DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT */
+  uint32_t flags;     /* DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT | DMPC_TUNED */
 } dmpc_config;
+
+/* How a forward is launched.  None of these changes the arithmetic of the
+ * persistent form (its results are bitwise the same for every choice); the
+ * per-launch form agrees with it to rounding (it forms A_t, B_t in a separate
+ * launch). */
+typedef struct {
+  int32_t plain;          /* 1: per-launch form (3 launches per iteration); 0: one persistent launch */
+  int32_t lpt;            /* persistent: take instances by decreasing T_b (needs the T array) */
+  int32_t waves_per_simd; /* persistent: 1 = registers uncapped; 2 = capped at 256 so that two waves
+                             share a SIMD (helps when there are more instances than 4 per SIMD) */
+  int32_t grid_mode;      /* persistent: 0 = as many waves as fit at once, popping four-instance units
+                             from a queue; 1 = one wave per four-instance unit */
+  float ms;               /* dmpc_autotune: measured forward time of this choice (ms); else 0 */
+} dmpc_launch_choice;
 
 typedef struct dmpc_handle_s* dmpc_handle;
 
@@ -159,6 +176,30 @@ int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, c
 /* Number of kernel launches the last dmpc_forward / dmpc_backward issued on
  * this handle (host-side count; for tests of the launch structure). */
 int dmpc_last_launch_count(dmpc_handle h);
+
+/* Autotuner (the persistent-batching row of the scope: launch structure
+ * picked per problem shape).  Runs the forward once per candidate launch
+ * choice (the per-launch form; the persistent form for each waves-per-SIMD
+ * cap, grid mode and, when T is given, instance order), times each with HIP
+ * events on `stream` (best of three after a warm-up), and stores the fastest
+ * on the handle under the shape (B, T_max, cost_kind, DMPC_NEED_GRAD,
+ * ckpt_every > 0, T given).  Arguments as dmpc_forward; on return the outputs
+ * and the workspace hold a forward with the chosen launch.  Unlike every other
+ * entry point it synchronises `stream` (it measures), so it cannot be
+ * captured in a graph; call it once before capturing.  `chosen` may be NULL. */
+int dmpc_autotune(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* x0, const float* Q,
+                  const float* p, const float* u_lo, const float* u_hi, const int32_t* T, float* u_out,
+                  float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes, void* stream,
+                  dmpc_launch_choice* chosen);
+
+/* Store (set) or read (get) the launch choice for the shape of cfg, with
+ * has_T != 0 for calls that pass a T array.  get returns DMPC_EINVAL when no
+ * choice is stored; set rejects out-of-range fields with DMPC_EINVAL. */
+int dmpc_set_tuned(dmpc_handle h, const dmpc_config* cfg, int has_T, const dmpc_launch_choice* choice);
+int dmpc_get_tuned(dmpc_handle h, const dmpc_config* cfg, int has_T, dmpc_launch_choice* choice);
+
+/* The launch choice the last dmpc_forward / dmpc_autotune on this handle used. */
+int dmpc_last_launch_choice(dmpc_handle h, dmpc_launch_choice* choice);
 
 /* Graph helpers: begin capturing `stream`; enqueue dmpc_forward/dmpc_backward
  * calls; end the capture into an executable graph.  The captured work uses

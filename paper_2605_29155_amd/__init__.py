@@ -17,7 +17,7 @@ from . import build as _build
 
 NX, NU, NZ, NPACK = 13, 4, 17, 153
 COST_DIAG, COST_DENSE = 0, 1
-NEED_GRAD, PLAIN, LPT = 0x1, 0x2, 0x4
+NEED_GRAD, PLAIN, LPT, TUNED = 0x1, 0x2, 0x4, 0x8
 ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_FP64, ST_QPMAXITER, ST_REGULARIZED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 ITERS_SHIFT = 8
 ALPHA_NONE = 255
@@ -34,6 +34,14 @@ class Config(C.Structure):
                 ("flags", C.c_uint32)]
 
 
+class LaunchChoice(C.Structure):
+    _fields_ = [("plain", C.c_int32), ("lpt", C.c_int32), ("waves_per_simd", C.c_int32), ("grid_mode", C.c_int32),
+                ("ms", C.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class DMPCError(RuntimeError):
     pass
 
@@ -48,6 +56,10 @@ def lib():
         if not os.path.exists(_build.LIB):
             raise DMPCError("libdmpc.so is not built (run paper_2605_29155_amd/build.py); "
                             "there is no fallback path")
+        # Streams and device pointers come from PyTorch, so the library must
+        # bind to the HIP runtime PyTorch loaded (PyTorch ships its own copy
+        # under the same soname): import torch first, then load the library.
+        import torch  # noqa: F401
         L = C.CDLL(_build.LIB)
         vp, sz, i32 = C.c_void_p, C.c_size_t, C.c_int
         L.dmpc_create.argtypes = [C.POINTER(vp), i32]
@@ -58,6 +70,10 @@ def lib():
         L.dmpc_forward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 9 + [vp, sz, vp, vp]
         L.dmpc_backward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 5 + [sz] + [vp] * 5 + [vp]
         L.dmpc_last_launch_count.argtypes = [vp]
+        L.dmpc_autotune.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 9 + [vp, sz, vp, C.POINTER(LaunchChoice)]
+        L.dmpc_set_tuned.argtypes = [vp, C.POINTER(Config), i32, C.POINTER(LaunchChoice)]
+        L.dmpc_get_tuned.argtypes = [vp, C.POINTER(Config), i32, C.POINTER(LaunchChoice)]
+        L.dmpc_last_launch_choice.argtypes = [vp, C.POINTER(LaunchChoice)]
         L.dmpc_capture_begin.argtypes = [vp, vp]
         L.dmpc_capture_end.argtypes = [vp, vp, C.POINTER(vp)]
         L.dmpc_graph_launch.argtypes = [vp, vp, vp]
@@ -148,6 +164,33 @@ def forward_raw(h, cfg, params, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, w
     h.check(rc, "dmpc_forward")
 
 
+def autotune(h, cfg, params, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, ws, stream=None):
+    """Time every launch choice on these inputs and store the fastest on the
+    handle for this shape (synchronises the stream).  Returns the choice."""
+    c = LaunchChoice()
+    rc = lib().dmpc_autotune(h._h, C.byref(cfg), params, _ptr(x0), _ptr(Q), _ptr(p), _ptr(u_lo), _ptr(u_hi),
+                             _ptr(T, "int32"), _ptr(u_out), _ptr(x_out), _ptr(status, "int32"), _ptr(ws, "uint8"),
+                             ws.numel(), _stream(stream), C.byref(c))
+    h.check(rc, "dmpc_autotune")
+    return c
+
+
+def set_tuned(h, cfg, has_T, choice):
+    h.check(lib().dmpc_set_tuned(h._h, C.byref(cfg), int(bool(has_T)), C.byref(choice)), "dmpc_set_tuned")
+
+
+def get_tuned(h, cfg, has_T):
+    c = LaunchChoice()
+    rc = lib().dmpc_get_tuned(h._h, C.byref(cfg), int(bool(has_T)), C.byref(c))
+    return None if rc != 0 else c
+
+
+def last_launch_choice(h):
+    c = LaunchChoice()
+    h.check(lib().dmpc_last_launch_choice(h._h, C.byref(c)), "dmpc_last_launch_choice")
+    return c
+
+
 def backward_raw(h, cfg, params, Q, p, u_lo, u_hi, ws, grad_u, grad_x, grad_Q, grad_p, grad_x0, stream=None):
     """params, Q, p, u_lo, u_hi: the forward's inputs (read only with
     checkpointing, may be None otherwise)."""
@@ -197,7 +240,10 @@ def _make_function():
             u = torch.empty(B, Tm, NU, device=p.device, dtype=torch.float32)
             x = torch.empty(B, Tm, NX, device=p.device, dtype=torch.float32)
             st = torch.empty(B, device=p.device, dtype=torch.int32)
-            forward_raw(layer.handle, cfg, layer.params, x0, Q, p, u_lo, u_hi, T, u, x, st, ws)
+            if layer.autotune and get_tuned(layer.handle, cfg, T is not None) is None:
+                autotune(layer.handle, cfg, layer.params, x0, Q, p, u_lo, u_hi, T, u, x, st, ws)
+            else:
+                forward_raw(layer.handle, cfg, layer.params, x0, Q, p, u_lo, u_hi, T, u, x, st, ws)
             ctx.cfg, ctx.ws, ctx.layer = cfg, ws, layer
             # the checkpointed backward recomputes stage factors from the inputs
             ctx.inputs = (Q, p, u_lo, u_hi) if cfg.ckpt_every > 0 else (None,) * 4
@@ -235,14 +281,18 @@ class DMPCLayer:
     """Callable layer: (x0, Q, p, u_lo, u_hi, T=None) -> (u*, x*, status)."""
 
     def __init__(self, params, max_iter=5, tol_du=0.0, cost_kind=COST_DIAG, plain=False, lpt=True,
-                 fp64_pivot=1e-6, ckpt_every=0, device=0):
+                 fp64_pivot=1e-6, ckpt_every=0, autotune=False, device=0):
+        """autotune: on the first call for a shape, time the launch choices
+        (dmpc_autotune) and use the fastest for that shape from then on."""
         self.handle = Handle(device)
+        self.autotune = autotune
         self.params = quad_params(params) if isinstance(params, dict) else params
         self.max_iter, self.tol_du, self.cost_kind = max_iter, tol_du, cost_kind
         self.plain, self.lpt, self.fp64_pivot, self.ckpt_every = plain, lpt, fp64_pivot, ckpt_every
 
     def config(self, B, T_max, need_grad=True):
         flags = (NEED_GRAD if need_grad else 0) | (PLAIN if self.plain else 0) | (LPT if self.lpt else 0)
+        flags |= TUNED if self.autotune else 0
         return make_config(B, T_max, self.cost_kind, self.max_iter, self.tol_du, flags, self.fp64_pivot,
                            self.ckpt_every)
 

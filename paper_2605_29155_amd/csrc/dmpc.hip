@@ -12,7 +12,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
+#include <vector>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -596,8 +599,11 @@ __device__ __forceinline__ void grp_write_state(const KArgs& A, const Grp& G, in
 // persistent forward
 // ---------------------------------------------------------------------------
 
-template <bool DENSE>
-__global__ __launch_bounds__(64) void k_fwd_persistent(KArgs A) {
+// OCC: waves per SIMD the register allocation is capped for (1: no cap beyond
+// the 512-register file; 2: at most 256 registers, two waves share a SIMD and
+// hide each other's latency when there are more waves than SIMDs).
+template <bool DENSE, int OCC>
+__global__ __launch_bounds__(64, OCC) void k_fwd_persistent(KArgs A) {
   __shared__ double lds[4 * L_REG];
   const int lane = threadIdx.x, grp = lane >> 4, l = lane & 15;
   double* L = lds + grp * L_REG;
@@ -951,7 +957,7 @@ int check_cfg(const dmpc_config* c) {
   if (c->cost_kind != DMPC_COST_DIAG && c->cost_kind != DMPC_COST_DENSE) return DMPC_EUNSUPPORTED;
   if (c->ckpt_every < 0) return DMPC_EINVAL;
   if (!(c->tol_du == c->tol_du) || !(c->fp64_pivot == c->fp64_pivot)) return DMPC_EINVAL;
-  if (c->flags & ~(DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT)) return DMPC_EINVAL;
+  if (c->flags & ~(DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT | DMPC_TUNED)) return DMPC_EINVAL;
   return DMPC_OK;
 }
 
@@ -1009,8 +1015,11 @@ thread_local std::string g_err;
 struct dmpc_handle_s {
   int device = 0;
   int cu = 0;
-  int occ[2] = {1, 1};
+  int occ[2][2] = {{1, 1}, {1, 1}};  // resident workgroups per CU: [dense][waves-per-SIMD variant]
   int last_launches = 0;
+  dmpc_launch_choice last_choice{};
+  // launch choices found by dmpc_autotune (or set), per problem shape
+  std::map<std::array<int, 6>, dmpc_launch_choice> tuned;
   std::string err;
 };
 
@@ -1074,6 +1083,108 @@ KArgs base_args(const dmpc_config* c, void* workspace) {
   return A;
 }
 
+// problem shape a tuned launch choice applies to
+std::array<int, 6> shape_key(const dmpc_config* c, bool has_T) {
+  return {c->B, c->T_max, c->cost_kind, (int)(c->flags & DMPC_NEED_GRAD), c->ckpt_every > 0 ? 1 : 0, has_T ? 1 : 0};
+}
+
+dmpc_launch_choice default_choice(const dmpc_config* c) {
+  dmpc_launch_choice d{};
+  d.plain = (c->flags & DMPC_PLAIN) ? 1 : 0;
+  d.lpt = (c->flags & DMPC_LPT) ? 1 : 0;
+  d.waves_per_simd = 1;
+  d.grid_mode = 0;
+  d.ms = 0.f;
+  return d;
+}
+
+int forward_args(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* x0, const float* Q,
+                 const float* p, const float* u_lo, const float* u_hi, const int32_t* T, float* u_out,
+                 float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes, uint8_t* decision_log,
+                 KArgs& A) {
+  if (!h) return fail(nullptr, DMPC_EINVAL, "NULL handle");
+  int rc = check_cfg(cfg);
+  if (rc) return fail(h, rc, "invalid configuration");
+  h->last_launches = 0;
+  if (cfg->B == 0) return DMPC_OK;
+  if (!x0 || !Q || !p || !u_lo || !u_hi || !u_out || !status)
+    return fail(h, DMPC_EINVAL, "NULL required pointer");
+  if (!(dyn.mass > 0.f) || !(dyn.Jxx > 0.f) || !(dyn.Jyy > 0.f) || !(dyn.Jzz > 0.f) || !(dyn.dt > 0.f))
+    return fail(h, DMPC_EINVAL, "non-positive mass, inertia or step");
+  const Layout L = make_layout(cfg);
+  if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace & 255))
+    return fail(h, DMPC_EWORKSPACE, "workspace missing, misaligned or smaller than dmpc_workspace_bytes()");
+  rc = hip_check(h, hipSetDevice(h->device), "hipSetDevice");
+  if (rc) return rc;
+  A = base_args(cfg, workspace);
+  A.P = make_dyn(dyn);
+  A.x0 = x0;
+  A.Q = Q;
+  A.p = p;
+  A.lo = u_lo;
+  A.hi = u_hi;
+  A.T = T;
+  A.u_out = u_out;
+  A.x_out = x_out;
+  A.status = status;
+  A.dlog = decision_log;
+  return DMPC_OK;
+}
+
+template <bool DENSE>
+void launch_persistent(int occ, int grid, hipStream_t s, const KArgs& A) {
+  if (occ == 2) k_fwd_persistent<DENSE, 2><<<grid, 64, 0, s>>>(A);
+  else k_fwd_persistent<DENSE, 1><<<grid, 64, 0, s>>>(A);
+}
+
+int launch_forward(dmpc_handle h, const dmpc_config* cfg, KArgs A, const int32_t* T, const dmpc_launch_choice& c,
+                   hipStream_t s) {
+  const bool dense = cfg->cost_kind == DMPC_COST_DENSE;
+  const int nq = A.nquads;
+  int launches = 0;
+  if (c.plain) {
+    const long long units = (long long)cfg->B * cfg->T_max;
+    const int lin_grid = (int)((units + 3) / 4);
+    k_plain_init<<<nq, 64, 0, s>>>(A);
+    ++launches;
+    for (int k = 0; k < cfg->max_iter; ++k) {
+      k_plain_lin<<<lin_grid, 64, 0, s>>>(A, 0);
+      if (dense) k_plain_riccati<true, 0><<<nq, 64, 0, s>>>(A);
+      else k_plain_riccati<false, 0><<<nq, 64, 0, s>>>(A);
+      if (dense) k_plain_ls<true><<<nq, 64, 0, s>>>(A);
+      else k_plain_ls<false><<<nq, 64, 0, s>>>(A);
+      launches += 3;
+    }
+    if (A.need_grad) {
+      k_plain_lin<<<lin_grid, 64, 0, s>>>(A, 1);
+      if (A.ckpt > 0) {
+        if (dense) k_plain_riccati<true, 2><<<nq, 64, 0, s>>>(A);
+        else k_plain_riccati<false, 2><<<nq, 64, 0, s>>>(A);
+      } else {
+        if (dense) k_plain_riccati<true, 1><<<nq, 64, 0, s>>>(A);
+        else k_plain_riccati<false, 1><<<nq, 64, 0, s>>>(A);
+      }
+      launches += 2;
+    }
+    k_plain_finalize<<<nq, 64, 0, s>>>(A);
+    ++launches;
+  } else {
+    const bool lpt = c.lpt && T;
+    A.use_order = lpt ? 1 : 0;
+    if (lpt) k_sort_by_T<<<1, 1024, 0, s>>>(T, cfg->B, cfg->T_max, A.ws.order, A.ws.queue);
+    else k_reset_queue<<<1, 64, 0, s>>>(A.ws.queue);
+    const int occ = c.waves_per_simd == 2 ? 2 : 1;
+    const int cap = std::max(1, h->cu * h->occ[dense ? 1 : 0][occ - 1]);
+    const int grid = c.grid_mode == 1 ? nq : std::min(nq, cap);
+    if (dense) launch_persistent<true>(occ, grid, s, A);
+    else launch_persistent<false>(occ, grid, s, A);
+    launches += 2;
+  }
+  h->last_launches = launches;
+  h->last_choice = c;
+  return hip_check(h, hipGetLastError(), "kernel launch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -1106,10 +1217,14 @@ int dmpc_create(dmpc_handle* out, int device) {
   h->cu = prop.multiProcessorCount;
   (void)hipSetDevice(device);
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fwd_persistent<false>, 64, 0) == hipSuccess && occ > 0)
-    h->occ[0] = occ;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fwd_persistent<true>, 64, 0) == hipSuccess && occ > 0)
-    h->occ[1] = occ;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fwd_persistent<false, 1>, 64, 0) == hipSuccess && occ > 0)
+    h->occ[0][0] = occ;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fwd_persistent<true, 1>, 64, 0) == hipSuccess && occ > 0)
+    h->occ[1][0] = occ;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fwd_persistent<false, 2>, 64, 0) == hipSuccess && occ > 0)
+    h->occ[0][1] = occ;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fwd_persistent<true, 2>, 64, 0) == hipSuccess && occ > 0)
+    h->occ[1][1] = occ;
   rc = upload_pack_tables(h);
   if (rc) {
     delete h;
@@ -1132,78 +1247,100 @@ int dmpc_forward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, co
                  const float* p, const float* u_lo, const float* u_hi, const int32_t* T, float* u_out,
                  float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes, uint8_t* decision_log,
                  void* stream) {
-  if (!h) return fail(nullptr, DMPC_EINVAL, "NULL handle");
+  KArgs A;
+  int rc = forward_args(h, cfg, dyn, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, workspace, workspace_bytes,
+                        decision_log, A);
+  if (rc || cfg->B == 0) return rc;
+  dmpc_launch_choice c = default_choice(cfg);
+  if (cfg->flags & DMPC_TUNED) {
+    auto it = h->tuned.find(shape_key(cfg, T != nullptr));
+    if (it != h->tuned.end()) c = it->second;
+  }
+  return launch_forward(h, cfg, A, T, c, (hipStream_t)stream);
+}
+
+int dmpc_autotune(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* x0, const float* Q,
+                  const float* p, const float* u_lo, const float* u_hi, const int32_t* T, float* u_out,
+                  float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes, void* stream,
+                  dmpc_launch_choice* chosen) {
+  KArgs A;
+  int rc = forward_args(h, cfg, dyn, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, workspace, workspace_bytes,
+                        nullptr, A);
+  if (rc) return rc;
+  dmpc_launch_choice best = default_choice(cfg);
+  best.ms = 0.f;
+  if (cfg->B > 0) {
+    // candidates: per-launch form; persistent form x occupancy target x grid x order
+    std::vector<dmpc_launch_choice> cand;
+    cand.push_back(dmpc_launch_choice{1, 0, 1, 0, 0.f});
+    for (int occ = 1; occ <= 2; ++occ)
+      for (int grid = 0; grid <= 1; ++grid)
+        for (int lpt = 0; lpt <= (T ? 1 : 0); ++lpt) cand.push_back(dmpc_launch_choice{0, lpt, occ, grid, 0.f});
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    rc = hip_check(h, hipEventCreate(&e0), "hipEventCreate");
+    if (rc) return rc;
+    rc = hip_check(h, hipEventCreate(&e1), "hipEventCreate");
+    if (rc) {
+      (void)hipEventDestroy(e0);
+      return rc;
+    }
+    float best_ms = 0.f;
+    for (size_t i = 0; i < cand.size() && !rc; ++i) {
+      rc = launch_forward(h, cfg, A, T, cand[i], s);  // warm-up
+      float ms = 0.f;
+      for (int r = 0; r < 3 && !rc; ++r) {
+        rc = hip_check(h, hipEventRecord(e0, s), "hipEventRecord");
+        if (!rc) rc = launch_forward(h, cfg, A, T, cand[i], s);
+        if (!rc) rc = hip_check(h, hipEventRecord(e1, s), "hipEventRecord");
+        if (!rc) rc = hip_check(h, hipEventSynchronize(e1), "hipEventSynchronize");
+        float m = 0.f;
+        if (!rc) rc = hip_check(h, hipEventElapsedTime(&m, e0, e1), "hipEventElapsedTime");
+        if (!rc && (r == 0 || m < ms)) ms = m;
+      }
+      if (!rc && (i == 0 || ms < best_ms)) {
+        best_ms = ms;
+        best = cand[i];
+        best.ms = ms;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    // leave the outputs and the workspace of the chosen configuration
+    rc = launch_forward(h, cfg, A, T, best, s);
+    if (rc) return rc;
+  }
+  h->tuned[shape_key(cfg, T != nullptr)] = best;
+  if (chosen) *chosen = best;
+  return DMPC_OK;
+}
+
+int dmpc_set_tuned(dmpc_handle h, const dmpc_config* cfg, int has_T, const dmpc_launch_choice* choice) {
+  if (!h || !choice) return fail(h, DMPC_EINVAL, "NULL argument");
   int rc = check_cfg(cfg);
   if (rc) return fail(h, rc, "invalid configuration");
-  h->last_launches = 0;
-  if (cfg->B == 0) return DMPC_OK;
-  if (!x0 || !Q || !p || !u_lo || !u_hi || !u_out || !status)
-    return fail(h, DMPC_EINVAL, "NULL required pointer");
-  if (!(dyn.mass > 0.f) || !(dyn.Jxx > 0.f) || !(dyn.Jyy > 0.f) || !(dyn.Jzz > 0.f) || !(dyn.dt > 0.f))
-    return fail(h, DMPC_EINVAL, "non-positive mass, inertia or step");
-  const Layout L = make_layout(cfg);
-  if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace & 255))
-    return fail(h, DMPC_EWORKSPACE, "workspace missing, misaligned or smaller than dmpc_workspace_bytes()");
-  rc = hip_check(h, hipSetDevice(h->device), "hipSetDevice");
-  if (rc) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  KArgs A = base_args(cfg, workspace);
-  A.P = make_dyn(dyn);
-  A.x0 = x0;
-  A.Q = Q;
-  A.p = p;
-  A.lo = u_lo;
-  A.hi = u_hi;
-  A.T = T;
-  A.u_out = u_out;
-  A.x_out = x_out;
-  A.status = status;
-  A.dlog = decision_log;
-  const bool dense = cfg->cost_kind == DMPC_COST_DENSE;
-  const int nq = A.nquads;
-  int launches = 0;
-  if (cfg->flags & DMPC_PLAIN) {
-    const long long units = (long long)cfg->B * cfg->T_max;
-    const int lin_grid = (int)((units + 3) / 4);
-    k_plain_init<<<nq, 64, 0, s>>>(A);
-    ++launches;
-    for (int k = 0; k < cfg->max_iter; ++k) {
-      k_plain_lin<<<lin_grid, 64, 0, s>>>(A, 0);
-      if (dense) k_plain_riccati<true, 0><<<nq, 64, 0, s>>>(A);
-      else k_plain_riccati<false, 0><<<nq, 64, 0, s>>>(A);
-      if (dense) k_plain_ls<true><<<nq, 64, 0, s>>>(A);
-      else k_plain_ls<false><<<nq, 64, 0, s>>>(A);
-      launches += 3;
-    }
-    if (A.need_grad) {
-      k_plain_lin<<<lin_grid, 64, 0, s>>>(A, 1);
-      if (A.ckpt > 0) {
-        if (dense) k_plain_riccati<true, 2><<<nq, 64, 0, s>>>(A);
-        else k_plain_riccati<false, 2><<<nq, 64, 0, s>>>(A);
-      } else {
-        if (dense) k_plain_riccati<true, 1><<<nq, 64, 0, s>>>(A);
-        else k_plain_riccati<false, 1><<<nq, 64, 0, s>>>(A);
-      }
-      launches += 2;
-    }
-    k_plain_finalize<<<nq, 64, 0, s>>>(A);
-    ++launches;
-  } else {
-    const bool lpt = (cfg->flags & DMPC_LPT) && T;
-    if (lpt) {
-      A.use_order = 1;
-      k_sort_by_T<<<1, 1024, 0, s>>>(T, cfg->B, cfg->T_max, A.ws.order, A.ws.queue);
-    } else {
-      k_reset_queue<<<1, 64, 0, s>>>(A.ws.queue);
-    }
-    const int cap = std::max(1, h->cu * h->occ[dense ? 1 : 0]);
-    const int grid = std::min(nq, cap);
-    if (dense) k_fwd_persistent<true><<<grid, 64, 0, s>>>(A);
-    else k_fwd_persistent<false><<<grid, 64, 0, s>>>(A);
-    launches += 2;
-  }
-  h->last_launches = launches;
-  return hip_check(h, hipGetLastError(), "kernel launch");
+  if (choice->plain < 0 || choice->plain > 1 || choice->lpt < 0 || choice->lpt > 1 || choice->waves_per_simd < 1 ||
+      choice->waves_per_simd > 2 || choice->grid_mode < 0 || choice->grid_mode > 1)
+    return fail(h, DMPC_EINVAL, "launch choice out of range");
+  h->tuned[shape_key(cfg, has_T != 0)] = *choice;
+  return DMPC_OK;
+}
+
+int dmpc_get_tuned(dmpc_handle h, const dmpc_config* cfg, int has_T, dmpc_launch_choice* choice) {
+  if (!h || !choice) return fail(h, DMPC_EINVAL, "NULL argument");
+  int rc = check_cfg(cfg);
+  if (rc) return fail(h, rc, "invalid configuration");
+  auto it = h->tuned.find(shape_key(cfg, has_T != 0));
+  if (it == h->tuned.end()) return fail(h, DMPC_EINVAL, "no tuned launch choice for this shape");
+  *choice = it->second;
+  return DMPC_OK;
+}
+
+int dmpc_last_launch_choice(dmpc_handle h, dmpc_launch_choice* choice) {
+  if (!h || !choice) return fail(h, DMPC_EINVAL, "NULL argument");
+  *choice = h->last_choice;
+  return DMPC_OK;
 }
 
 int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* Q, const float* p,

@@ -95,3 +95,16 @@ def test_checkpoint_workspace(D):
     assert D.validate(D.make_config(4, 10, ckpt_every=-1)) == -1
     # stage factors: 1424 bytes per stage; checkpoints: 10 stages of factors + 4 x 1584 bytes
     assert full - ck >= 16384 * (50 - 10) * 1424 - 16384 * 4 * 1584
+
+
+def test_tuner_entry_points_host_checks(D):
+    cfg = D.make_config(64, 20, flags=D.TUNED)
+    assert D.validate(cfg) == 0
+    c = D.LaunchChoice(0, 1, 1, 0, 0.0)
+    L = D.lib()
+    assert L.dmpc_set_tuned(None, C.byref(cfg), 1, C.byref(c)) == -1
+    assert L.dmpc_get_tuned(None, C.byref(cfg), 1, C.byref(c)) == -1
+    assert L.dmpc_last_launch_choice(None, C.byref(c)) == -1
+    rc = L.dmpc_autotune(None, C.byref(cfg), D.QuadParams(), None, None, None, None, None, None, None, None, None,
+                         None, 0, None, None)
+    assert rc == -1
