@@ -167,6 +167,56 @@ def profile_short(d, t):
     print("profile-short: 2 x (fwd + bwd), then a %d-byte device copy" % n, flush=True)
 
 
+# Table I of the paper (solver latency, drone hover at random targets; RTX A6000 + i9-13900K):
+# (B, T) -> (CA-DiffMPC forward ms, CA-DiffMPC backward ms)
+PAPER_TABLE1 = {(1, 2): (0.93, 0.32), (1, 10): (1.08, 0.80), (1, 50): (1.84, 2.35),
+                (256, 2): (1.21, 0.38), (256, 10): (1.68, 0.87), (256, 50): (4.00, 2.60)}
+
+
+def latency_table(reps=20, warmup=3):
+    """Forward and backward latency of one call (HIP events on the call's
+    stream, median of `reps`) at the paper's latency shapes, hover-to-target
+    workload, K = 5 (the paper does not state K for this table)."""
+    import numpy as np
+    import torch
+
+    import paper_2605_29155_amd as D
+    import workloads as W
+    dev = "cuda:0"
+    h = D.Handle(0)
+    params = D.quad_params(W.quad_params_f32())
+    rows = []
+    for (B, T), (pf, pb) in PAPER_TABLE1.items():
+        d = W.make_hover_target(B, T)
+        t = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev) for k in ("x0", "Q", "p", "lo", "hi", "grad_u")}
+        cfg = D.make_config(B, T, D.COST_DIAG, d["K"], 0.0, D.NEED_GRAD)
+        ws = D.alloc_workspace(cfg, dev)
+        u = torch.empty(B, T, 4, device=dev)
+        x = torch.empty(B, T, 13, device=dev)
+        st = torch.empty(B, dtype=torch.int32, device=dev)
+        gQ, gp, gx0 = torch.empty_like(t["Q"]), torch.empty_like(t["p"]), torch.empty_like(t["x0"])
+        s = torch.cuda.Stream()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        fw, bw = [], []
+        with torch.cuda.stream(s):
+            for r in range(warmup + reps):
+                e[0].record(s)
+                D.forward_raw(h, cfg, params, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], None, u, x, st, ws, None, s)
+                e[1].record(s)
+                D.backward_raw(h, cfg, params, None, None, None, None, ws, t["grad_u"], None, gQ, gp, gx0, s)
+                e[2].record(s)
+                e[2].synchronize()
+                if r >= warmup:
+                    fw.append(e[0].elapsed_time(e[1]))
+                    bw.append(e[1].elapsed_time(e[2]))
+        f, b = float(np.median(fw)), float(np.median(bw))
+        rows.append(dict(B=B, T=T, K=d["K"], fwd_ms=f, bwd_ms=b, solves_per_s=B / ((f + b) * 1e-3),
+                         paper_fwd_ms=pf, paper_bwd_ms=pb, status_converged=None))
+        print("latency B=%3d T=%2d: fwd %.3f ms (paper %.2f)  bwd %.3f ms (paper %.2f)" % (B, T, f, pf, b, pb),
+              file=sys.stderr, flush=True)
+    return rows
+
+
 def cpu_baseline_leg(d, gpu, nsample=64):
     """Oracle on the host: time fwd + Riccati-adjoint bwd of the full batch on
     all host cores, and check the kernel on a sample with its decisions
@@ -218,6 +268,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--latency", action="store_true",
+                    help="forward / backward latency at the paper's Table I shapes (B 1 and 256, T 2, 10, 50) "
+                         "on a hover-to-target workload; prints one JSON line with the table")
     ap.add_argument("--profile-short", action="store_true",
                     help="for counter collection: two direct fwd+bwd calls of the persistent form, then a "
                          "256 MiB device copy whose FETCH_SIZE / WRITE_SIZE calibrate the HBM counters")
@@ -228,6 +281,10 @@ def main():
         sys.exit(2)
     import torch
     dev = "cuda:0"
+    if a.latency:
+        print(json.dumps({"latency_table": latency_table(), "workload": "hover_to_random_target, K=5",
+                          "paper_hardware": "NVIDIA RTX A6000 + Intel i9-13900K"}), flush=True)
+        return
     print("bench: building inputs (B=4096, T=20, MLP cost)", file=sys.stderr, flush=True)
     d, t = make_inputs(dev)
     if a.profile_short:

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 
 #include "dmpc.h"
 #include "dmpc_device.hpp"
@@ -37,13 +38,14 @@ struct Ws {
   float* tail;  // [B][tstride][TS]  stage factors for the backward: every stage,
                 //   or (checkpointing) one segment, recomputed by the backward
   float* ktil;  // [B][Tm][4]   (backward scratch)
-  double* ck;   // [B][nck][L_F] checkpoints of (V, v) at stages j * ckpt
+  double* ck;   // [B][nck][CK_W] checkpoints of (V, v) at stages j * ckpt
 };
 
 struct KArgs {
   Dyn P;
   int B, Tm, K, need_grad, use_order, nquads;
   int ckpt, nck, tstride;  // checkpoint interval (0 = off), checkpoints per instance, tail stages per instance
+  int has_lin;             // the workspace holds the per-launch form's linearisation buffer
   float tol, piv;
   const float *x0, *Q, *p, *lo, *hi;
   const int* T;
@@ -135,13 +137,14 @@ __device__ void grp_init(const KArgs& A, const Grp& G) {
   }
 }
 
-// LDS region of one instance (doubles).  V rows (stride 14), v, the F columns
-// owned by the 16 lanes (stride 14; once every lane has formed its column of
-// the stage Hessian the area holds each lane's Q_xx column instead), row 0 of
-// F^T V F by lane, the 4x4 control block with q_u, and the gain columns.  The
-// region stride (516 doubles = 4128 bytes) puts the four instances of a wave
-// on distinct LDS banks for broadcast reads.
-constexpr int L_V = 0, L_VV = 182, L_F = 198, L_QX = 198, L_Y0 = 422, L_H = 438, L_K = 462, L_REG = 516;
+// LDS region of one instance (doubles): the symmetric V being assembled (13
+// rows, stride 14), each lane's Q_xx column parked while the control block is
+// solved (stride 14), and one dummy slot per lane for the writes the V update
+// masks out.  Everything else a stage needs from other lanes comes through DPP
+// row broadcasts.
+constexpr int L_V = 0, L_QX = 198, L_DUM = 438, L_REG = 516;
+// checkpoint record (doubles): V rows at stride 14, v at CK_VV
+constexpr int CK_VV = 182, CK_W = 198;
 
 // orders the row's LDS traffic only (outstanding global loads stay in flight)
 __device__ __forceinline__ void lds_sync() {
@@ -170,7 +173,7 @@ __device__ __forceinline__ void lds_write(double* p, const double* v) {
 
 // One backward sweep t = t_hi-1 .. t_lo of the Riccati recursion (Sec. IV
 // "Backward pass with input bounds"), starting from V = v = 0 or from a
-// checkpoint (vinit, the LDS image of V and v at stage t_hi).  MODE 0: stagewise
+// checkpoint (vinit: a record of V and v at stage t_hi).  MODE 0: stagewise
 // box-QP, writes K_t, k_t to the gains and the pattern to the decision log.
 // MODE 1 (tail): the active set is fixed to the controls that sit on a bound,
 // writes F_t, K_t and the masked inverse of the free block for the backward at
@@ -181,26 +184,51 @@ __device__ __forceinline__ void lds_write(double* p, const double* v) {
 //
 // The stage algebra accumulates in FP64: without it the Schur-complement
 // update of V loses several digits on these costs.  Lane l forms column col(l)
-// of Q = C + F^T V F; operands shared by the row (V, F columns, gains, the
-// control block) go through the instance's LDS region and are read with
-// broadcast loads.  Known columns of F are used exactly: F[:,0..2] = e_0..e_2
+// of Q = C + F^T V F and keeps row l of V in registers; the operands a lane
+// needs from the others (rows of V, columns of F, row 0 of Q, the control
+// block, gain columns) arrive by 64-bit DPP row broadcasts (bc<L>), so the
+// contractions do not go through LDS.  Known columns of F are used exactly: F[:,0..2] = e_0..e_2
 // (nothing depends on position), F[:,7..9] = dt e_0..2 + e_7..9 (velocity only
 // drives position), and rows 10..12 of F[:,3..6] are zero (body rates do not
 // depend on the attitude).
+// value of v in lane L of this lane's 16-lane row (L a compile-time constant)
+template <int L>
+__device__ __forceinline__ double bc(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)x, 0x150 + L, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), 0x150 + L, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// f(integral_constant<0>) .. f(integral_constant<N-1>): a loop whose index
+// is a compile-time constant in the body (DPP lane selects must be)
+template <int... I, class F>
+__device__ __forceinline__ void sfor_impl(std::integer_sequence<int, I...>, F&& f) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+  sfor_impl(std::make_integer_sequence<int, N>{}, f);
+}
 template <bool DENSE, int MODE, bool LIN_INLINE>
 __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* L, uint32_t& st, int t_hi,
                           int t_lo = 0, const double* vinit = nullptr, int tbase = 0) {
   const int l = G.l, col = G.col, b = G.b, T = G.T;
   const double hdt = (double)A.P.h;
-  for (int i = l; i < L_F; i += 16) L[i] = vinit ? vinit[i] : 0.0;  // V, v at stage t_hi (zero at T)
-  lds_sync();
+  double Vr[NX], vl = 0.0;  // lane l < 13: row l of V and v_l at the stage being entered
+#pragma unroll
+  for (int j = 0; j < NX; ++j) Vr[j] = (vinit && l < NX) ? vinit[l * 14 + j] : 0.0;
+  if (vinit && l < NX) vl = vinit[CK_VV + l];
   float zn[NZ];
   if (t_hi > t_lo) load_z(traj_at(A, b, n, t_hi - 1), zn);
   for (int t = t_hi - 1; t >= t_lo; --t) {
     if (MODE == 2 && t + 1 < T && (t + 1) % A.ckpt == 0) {
       // V, v of stage t + 1 (complete since the last row sync): exact FP64 image
-      double* ck = A.ws.ck + ((size_t)b * A.nck + ((t + 1) / A.ckpt - 1)) * L_F;
-      for (int i = l; i < L_F; i += 16) ck[i] = L[i];
+      double* ck = A.ws.ck + ((size_t)b * A.nck + ((t + 1) / A.ckpt - 1)) * CK_W;
+      if (l < NX) {
+#pragma unroll
+        for (int j = 0; j < NX; ++j) ck[l * 14 + j] = Vr[j];
+        ck[CK_VV + l] = vl;
+      }
     }
     const float* zp = traj_at(A, b, n, t);
     float zb[NZ];
@@ -240,45 +268,37 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     double Fd[NX];
 #pragma unroll
     for (int k = 0; k < NX; ++k) Fd[k] = (double)Fc[k];
-    lds_write<NX>(L + L_F + l * 14, Fd);
-    lds_sync();
 
-    // Y[:, col] = V F[:, col]   (V symmetric: row k is column k)
+    // Y[:, col] = V F[:, col]: lane k holds row k of V (= column k)
     double Yc[NX];
 #pragma unroll
     for (int i = 0; i < NX; ++i) Yc[i] = 0.0;
+    sfor<NX>([&](auto K) {
+      constexpr int k = K;
 #pragma unroll
-    for (int k = 0; k < NX; ++k) {
-      double vk[NX];
-      lds_read<NX>(L + L_V + k * 14, vk);
-#pragma unroll
-      for (int i = 0; i < NX; ++i) Yc[i] = fma(vk[i], Fd[k], Yc[i]);
-    }
-    // Q[:, col] = (F^T V F)[:, col]
+      for (int i = 0; i < NX; ++i) Yc[i] = fma(bc<k>(Vr[i]), Fd[k], Yc[i]);
+    });
+    // Q[:, col] = (F^T V F)[:, col]; column i of F comes from lane lane_of(i)
     double Qc[NZ];
     Qc[0] = Yc[0];
     Qc[1] = Yc[1];
     Qc[2] = Yc[2];
 #pragma unroll
     for (int m = 0; m < 3; ++m) Qc[7 + m] = fma(hdt, Yc[m], Yc[7 + m]);
-#pragma unroll
-    for (int i = 3; i < 7; ++i) {
-      double f[10];
-      lds_read<10>(L + L_F + i * 14, f);
+    sfor<4>([&](auto I) {
+      constexpr int i = 3 + I;
       double s = 0.0;
 #pragma unroll
-      for (int k = 0; k < 10; ++k) s = fma(f[k], Yc[k], s);
+      for (int k = 0; k < 10; ++k) s = fma(bc<i>(Fd[k]), Yc[k], s);
       Qc[i] = s;
-    }
-#pragma unroll
-    for (int i = 10; i < NZ; ++i) {
-      double f[NX];
-      lds_read<NX>(L + L_F + lane_of(i) * 14, f);
+    });
+    sfor<7>([&](auto I) {
+      constexpr int i = 10 + I;
       double s = 0.0;
 #pragma unroll
-      for (int k = 0; k < NX; ++k) s = fma(f[k], Yc[k], s);
+      for (int k = 0; k < NX; ++k) s = fma(bc<lane_of(i)>(Fd[k]), Yc[k], s);
       Qc[i] = s;
-    }
+    });
 
     // stage cost: Q += C_t, q = g + F^T v with g = C_t z + c_t
     const size_t srow = (size_t)b * A.Tm + t;
@@ -310,36 +330,29 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
       }
     }
     double vv[NX];
-    lds_read<NX>(L + L_VV, vv);
+    sfor<NX>([&](auto K) { vv[K] = bc<K>(vl); });
 #pragma unroll
     for (int k = 0; k < NX; ++k) qc = fma(Fd[k], vv[k], qc);
     const double q0 = g0 + vv[0];
-    // publish row 0 entries and the control block
-    L[L_Y0 + l] = Yc[0];
-    if (col >= NX) {
-      double h4[4] = {Qc[13], Qc[14], Qc[15], Qc[16]};
-      lds_write<4>(L + L_H + (col - NX) * 4, h4);
-      L[L_H + 16 + (col - NX)] = qc;
-    }
-    lds_sync();
-    // every lane has read the F columns: park this lane's Q_xx column there
-    lds_write<NX>(L + L_QX + l * 14, Qc);
+    const double v00 = bc<0>(Vr[0]);
+    // control block and q_u from the lanes owning columns 13..16
     double H[16], qu[4];
-    {
-      double hr[16];
-      lds_read<16>(L + L_H, hr);  // hr[b*4 + a] = Q[13+a][13+b]
-      lds_read<4>(L + L_H + 16, qu);
+    sfor<4>([&](auto BB) {
+      constexpr int bb = BB;
 #pragma unroll
-      for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-        for (int a = 0; a <= bb; ++a) {
-          H[a * 4 + bb] = hr[bb * 4 + a];
-          H[bb * 4 + a] = hr[bb * 4 + a];
-        }
-    }
+      for (int a = 0; a <= bb; ++a) {
+        const double h = bc<lane_of(13 + bb)>(Qc[13 + a]);
+        H[a * 4 + bb] = h;
+        H[bb * 4 + a] = h;
+      }
+      qu[bb] = bc<lane_of(13 + bb)>(qc);
+    });
+    lds_write<NX>(L + L_QX + l * 14, Qc);
+    double y0b[16];  // Y[0, :] by lane (row 0 of Q without the cost)
+    sfor<16>([&](auto J) { y0b[J] = bc<J>(Yc[0]); });
     // row 0 of Q (lane 0's x-row; its own column is 16)
     auto R0 = [&](int j) -> double {
-      double r = (j == 0) ? L[L_V] + c00 : L[L_Y0 + lane_of(j)];
+      double r = (j == 0) ? v00 + c00 : y0b[lane_of(j)];
       if (DENSE && j > 0) r += (double)A.Q[srow * NPK + j];
       return r;
     };
@@ -377,37 +390,36 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
 #pragma unroll
     for (int a = 0; a < 4; ++a) Kd[a] = -Kd[a];
     const float Kc[4] = {(float)Kd[0], (float)Kd[1], (float)Kd[2], (float)Kd[3]};
-    if (l < NX) lds_write<4>(L + L_K + l * 4, Kd);
-    lds_sync();
-
     // V row l = Q_xx[l, :] + Q_ux[:, l]^T K ;  v_l = Q_x[l] + Q_ux[:, l]^T k
-    // (gain columns streamed from LDS, V entries written straight back).
-    // V is kept exactly symmetric: lane l forms the entries j >= l of its row
-    // and writes each to (l, j) and (j, l).  The rows are read as columns in
-    // the next stage, and an antisymmetric rounding residue would otherwise be
-    // carried and amplified from stage to stage over long horizons (the
-    // control-limited DDP of Tassa et al. 2014, cited for the Riccati pass in
-    // Sec. IV, likewise keeps V symmetric).
+    // (gain column j broadcast from lane j).  V is kept exactly symmetric:
+    // lane l forms the entries j >= l of its row and writes each to (l, j) and
+    // (j, l) (the others go to its dummy slot, which keeps the loop free of
+    // branches), then every lane reads its row back.  Row k of V is used as
+    // column k in the next stage, and an antisymmetric rounding residue would
+    // otherwise be carried and amplified from stage to stage over long
+    // horizons (the control-limited DDP of Tassa et al. 2014, cited for the
+    // Riccati pass in Sec. IV, likewise keeps V symmetric).
+    double R0r[NX];
+#pragma unroll
+    for (int j = 0; j < NX; ++j) R0r[j] = (j == 0) ? v00 + c00 : R0(j);
     if (l < NX) {
       double vi = (l == 0) ? q0 : qc;
 #pragma unroll
       for (int a = 0; a < 4; ++a) vi = fma(Qux[a], kv[a], vi);
-      const double v00 = L[L_V];
+      sfor<NX>([&](auto J) {
+        constexpr int j = J;
+        double s = (l == 0) ? R0r[j] : L[L_QX + l * 14 + j];
 #pragma unroll
-      for (int j = 0; j < NX; ++j) {
-        double kj[4];
-        lds_read<4>(L + L_K + j * 4, kj);
-        double s = (l == 0) ? (j == 0 ? v00 + c00 : R0(j)) : L[L_QX + l * 14 + j];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) s = fma(Qux[a], kj[a], s);
-        if (j >= l) {
-          L[L_V + l * 14 + j] = s;
-          if (j > l) L[L_V + j * 14 + l] = s;
-        }
-      }
-      L[L_VV + l] = vi;
+        for (int a = 0; a < 4; ++a) s = fma(Qux[a], bc<j>(Kd[a]), s);
+        const int a1 = (j >= l) ? (L_V + l * 14 + j) : (L_DUM + l);
+        const int a2 = (j > l) ? (L_V + j * 14 + l) : (L_DUM + l);
+        L[a1] = s;
+        L[a2] = s;
+      });
+      vl = vi;
     }
     lds_sync();
+    if (l < NX) lds_read<NX>(L + L_V + l * 14, Vr);
 
     if (MODE == 0) {
       if (l < NX) {
@@ -823,7 +835,7 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
   // factors of stages [a, e) into the tail at index t - a
   auto recompute = [&](int a, int e) {
     uint32_t st = 0;
-    const double* vinit = (e < T) ? A.ws.ck + ((size_t)b * A.nck + (e / seg - 1)) * L_F : nullptr;
+    const double* vinit = (e < T) ? A.ws.ck + ((size_t)b * A.nck + (e / seg - 1)) * CK_W : nullptr;
     grp_sweep<DENSE, 1, true>(A, G, n, 0, L, st, e, a, vinit, a);
     mem_fence_wg();
   };
@@ -946,6 +958,7 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
 struct Layout {
   size_t state, queue, order, traj, gains, lin, tail, ktil, ck, total;
   int tstride, nck;
+  bool has_lin;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -975,7 +988,10 @@ Layout make_layout(const dmpc_config* c) {
   L.order = take(B * sizeof(int));
   L.traj = take(B * NSLOT * Tm * ZS * sizeof(float));
   L.gains = take(B * Tm * GS * sizeof(float));
-  L.lin = (c->flags & DMPC_PLAIN) ? take(B * Tm * FS * sizeof(float)) : take(0);
+  // the per-launch form's linearisation buffer: present when that form may run
+  // (requested, or possibly chosen by a tuned launch)
+  L.has_lin = (c->flags & (DMPC_PLAIN | DMPC_TUNED)) != 0;
+  L.lin = L.has_lin ? take(B * Tm * FS * sizeof(float)) : take(0);
   const bool g = (c->flags & DMPC_NEED_GRAD) != 0;
   const int ck = c->ckpt_every;
   // checkpointing keeps one segment of factors per instance (the backward's
@@ -984,7 +1000,7 @@ Layout make_layout(const dmpc_config* c) {
   L.nck = (ck > 0) ? (c->T_max - 1) / ck : 0;
   L.tail = take(g ? B * (size_t)L.tstride * TS * sizeof(float) : 0);
   L.ktil = take(g ? B * Tm * 4 * sizeof(float) : 0);
-  L.ck = take(g ? B * (size_t)L.nck * L_F * sizeof(double) : 0);
+  L.ck = take(g ? B * (size_t)L.nck * CK_W * sizeof(double) : 0);
   L.total = off;
   return L;
 }
@@ -1080,6 +1096,7 @@ KArgs base_args(const dmpc_config* c, void* workspace) {
   A.ckpt = c->ckpt_every;
   A.nck = L.nck;
   A.tstride = L.tstride;
+  A.has_lin = L.has_lin ? 1 : 0;
   return A;
 }
 
@@ -1142,6 +1159,8 @@ int launch_forward(dmpc_handle h, const dmpc_config* cfg, KArgs A, const int32_t
   const bool dense = cfg->cost_kind == DMPC_COST_DENSE;
   const int nq = A.nquads;
   int launches = 0;
+  if (c.plain && !A.has_lin)
+    return fail(h, DMPC_EWORKSPACE, "the per-launch form needs a workspace sized with DMPC_PLAIN or DMPC_TUNED");
   if (c.plain) {
     const long long units = (long long)cfg->B * cfg->T_max;
     const int lin_grid = (int)((units + 3) / 4);
@@ -1272,7 +1291,7 @@ int dmpc_autotune(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, c
   if (cfg->B > 0) {
     // candidates: per-launch form; persistent form x occupancy target x grid x order
     std::vector<dmpc_launch_choice> cand;
-    cand.push_back(dmpc_launch_choice{1, 0, 1, 0, 0.f});
+    if (A.has_lin) cand.push_back(dmpc_launch_choice{1, 0, 1, 0, 0.f});
     for (int occ = 1; occ <= 2; ++occ)
       for (int grid = 0; grid <= 1; ++grid)
         for (int lpt = 0; lpt <= (T ? 1 : 0); ++lpt) cand.push_back(dmpc_launch_choice{0, lpt, occ, grid, 0.f});

@@ -108,3 +108,12 @@ def test_tuner_entry_points_host_checks(D):
     rc = L.dmpc_autotune(None, C.byref(cfg), D.QuadParams(), None, None, None, None, None, None, None, None, None,
                          None, 0, None, None)
     assert rc == -1
+
+
+def test_tuned_workspace_holds_the_per_launch_buffer(D):
+    # a tuned launch may pick the per-launch form, whose linearisation buffer
+    # (B x T x 272 floats) must then be part of the workspace
+    plain = D.workspace_bytes(D.make_config(256, 20, flags=D.NEED_GRAD | D.PLAIN))
+    tuned = D.workspace_bytes(D.make_config(256, 20, flags=D.NEED_GRAD | D.TUNED))
+    pers = D.workspace_bytes(D.make_config(256, 20, flags=D.NEED_GRAD))
+    assert tuned == plain and tuned - pers >= 256 * 20 * 272 * 4

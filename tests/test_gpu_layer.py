@@ -182,8 +182,7 @@ def test_long_horizon_parity():
     becomes ill-conditioned): every instance within the unscaled bars.  This
     catches precision loss that compounds along the horizon in the Riccati
     recursion, such as an asymmetric rounding residue in V."""
-    d = W.make(3, B=256, seed=3003)
-    d["T"] = np.full(256, d["T_max"], np.int32)
+    d = W.make(1, B=256, T=50, seed=3003)
     d["grad_u"] = np.random.default_rng(7).standard_normal((256, d["T_max"], 4)).astype(np.float32)
     g = run_gpu(d, K=3, tol=0.0)
     o = oracle_replay(d, g)

@@ -121,3 +121,29 @@ def test_fixed_control_bounds():
     assert np.all(g["u"][:, :, 1] == 2.0)
     o = oracle_replay(d, g)
     check_parity(d, g, o, "fixed rotor")
+
+
+def test_fp64_pivot_flag_and_tiny_control_weight():
+    """Adversarial set: R scaled to 1e-8.  The control block is always
+    factored in FP64, so fp64_pivot only decides which stages are flagged:
+    the results are bitwise the same for every threshold, a threshold above
+    every pivot flags every instance and a non-positive one flags none.
+    Parity with the oracle at the conditioning-scaled bars (R = 1e-8 makes
+    the stage QPs far more ill-conditioned than the workloads)."""
+    from gpu_util import oracle_sensitivity
+    d = W.make(0, B=64, r_scale=1e-6, seed=2006)
+    a = run_gpu(d, fp64_pivot=1e-6)
+    b = run_gpu(d, fp64_pivot=1e9)
+    c = run_gpu(d, fp64_pivot=0.0)
+    assert np.all((b["status"] & 0x8) != 0)
+    assert not np.any(c["status"] & 0x8)
+    for k in ("u", "x", "dQ", "dp", "dx0", "dlog"):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
+    o = oracle_replay(d, a)
+    eu = rel(a["u"], o["replay"]["u"])
+    eg = np.max([rel(a[k], o["bwd"][k]) for k in ("dQ", "dp", "dx0")], axis=0)
+    s = oracle_sensitivity(d, o)
+    scale = np.maximum(1.0, s / 1e-6)
+    print("R=1e-8: flagged at 1e-6 %d/64 | u* max %.2e grads max %.2e | sensitivity max %.1e"
+          % (np.sum((a["status"] & 0x8) != 0), eu.max(), eg.max(), s.max()), flush=True)
+    assert np.all(eu <= TOL_U * scale) and np.all(eg <= TOL_G * scale)

@@ -37,10 +37,10 @@ def _run(D, h, cfg, par, t, o):
 
 def test_every_persistent_choice_is_bitwise_identical():
     import paper_2605_29155_amd as D
-    d = W.make(3, B=96, T=30, seed=5003)
+    d = W.make(3, B=96, T=20, seed=5003)
     dev = "cuda:0"
     h = handle()
-    cfg = D.make_config(96, 30, 0, 4, 1e-5, D.NEED_GRAD | D.TUNED)
+    cfg = D.make_config(96, 20, 0, 4, 1e-5, D.NEED_GRAD | D.TUNED)
     par = D.quad_params(W.quad_params_f32())
     t, o = _bufs(d, cfg, dev)
     ref = None
@@ -60,7 +60,9 @@ def test_every_persistent_choice_is_bitwise_identical():
     D.set_tuned(h, cfg, True, D.LaunchChoice(1, 0, 1, 0, 0.0))
     r = _run(D, h, cfg, par, t, o)
     assert D.last_launch_choice(h).plain == 1
-    assert rel(r["u"], ref["u"]).max() <= 1e-5 and rel(r["gp"], ref["gp"]).max() <= 1e-4
+    du, dg = rel(r["u"], ref["u"]).max(), rel(r["gp"], ref["gp"]).max()
+    print("per-launch vs persistent: u %.2e dp %.2e" % (du, dg), flush=True)
+    assert du <= 1e-5 and dg <= 1e-4
 
 
 def test_autotune_stores_and_reuses_its_choice():

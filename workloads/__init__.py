@@ -106,11 +106,13 @@ class CostMLP:
         return Q, p
 
 
-def make(cfg_id, B=None, T=None, seed=None, pu_scale=1.0):
+def make(cfg_id, B=None, T=None, seed=None, pu_scale=1.0, r_scale=1.0):
     """Return the inputs of a workload as a dict of numpy arrays (float32) plus
     metadata.  B / T / seed override the configuration's values (smaller
     instances of the same distribution for tests).  pu_scale multiplies the
-    control part of p (0.01 gives non-trivial free sets; default 1)."""
+    control part of p (0.01 gives non-trivial free sets; default 1).  r_scale
+    multiplies the control weight R of a diagonal cost (1e-6 gives R = 1e-8,
+    the adversarial set whose Cholesky pivots fall below 1e-6)."""
     c = dict(CONFIGS[cfg_id])
     B = c["B"] if B is None else B
     Tm = c["T"] if T is None else T
@@ -124,6 +126,7 @@ def make(cfg_id, B=None, T=None, seed=None, pu_scale=1.0):
     gate = None
     if c["cost"] == "diag":
         Q = _diag_cost(rng, B, Tm)
+        Q[..., NX:] *= r_scale
         p = rng.standard_normal((B, Tm, NZ))
     elif c["cost"] == "dense":
         Q = _wishart_packed(rng, B, Tm)
@@ -175,3 +178,33 @@ def make(cfg_id, B=None, T=None, seed=None, pu_scale=1.0):
     out["Q"][pad] = 0.0
     out["p"][pad] = 0.0
     return out
+
+
+def make_hover_target(B, T, seed=1100, K=5):
+    """Hover-to-target latency workload (the shapes of the paper's solver
+    latency measurement, Sec. V-A / Table I): x0 is hover at the origin with
+    N(0, 0.1) noise on position and velocity; each instance is asked to hover
+    at a target position drawn uniformly in [-1, 1]^3 m.  The stage cost is
+    1/2 (z - z_ref)^T C (z - z_ref) with C = diag(10 on position, 1 on the
+    quaternion, 1 on velocity, 0.1 on body rates, 0.01 on the thrusts) and
+    z_ref = (target, level attitude, zero velocity and rates, hover thrust),
+    i.e. c = -C z_ref.  Controls boxed to [0, 8.5] N."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x0 = hover_state(B)
+    x0[:, 0:3] += rng.normal(0.0, 0.1, size=(B, 3))
+    x0[:, 7:10] += rng.normal(0.0, 0.1, size=(B, 3))
+    target = rng.uniform(-1.0, 1.0, size=(B, 3))
+    qd = np.array([10.0] * 3 + [1.0] * 4 + [1.0] * 3 + [0.1] * 3 + [0.01] * 4)
+    hover_u = QUAD["mass"] * QUAD["g"] / 4.0
+    zref = np.zeros((B, NZ))
+    zref[:, 0:3] = target
+    zref[:, 3] = 1.0
+    zref[:, NX:] = hover_u
+    Q = np.broadcast_to(qd, (B, T, NZ)).copy()
+    p = -(Q * zref[:, None, :])
+    lo = np.zeros((B, NU))
+    hi = np.full((B, NU), 8.5)
+    grad_u = rng.standard_normal((B, T, NU))
+    return dict(x0=x0.astype(np.float32), Q=Q.astype(np.float32), p=p.astype(np.float32), lo=lo.astype(np.float32),
+                hi=hi.astype(np.float32), T=np.full(B, T, np.int32), grad_u=grad_u.astype(np.float32), K=K, tol=0.0,
+                T_max=T, B=B, cost_kind=0, ckpt=0, cfg="hover")
