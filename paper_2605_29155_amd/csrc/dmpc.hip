@@ -186,11 +186,75 @@ __device__ __forceinline__ void lds_write(double* p, const double* v) {
 // update of V loses several digits on these costs.  Lane l forms column col(l)
 // of Q = C + F^T V F and keeps row l of V in registers; the operands a lane
 // needs from the others (rows of V, columns of F, row 0 of Q, the control
-// block, gain columns) arrive by 64-bit DPP row broadcasts (bc<L>), so the
+// block, gain columns) arrive by 64-bit DPP row broadcasts, fused into the
+// FMAs that consume them (y_block, q_block_*, v_block, fv_chain), so the
 // contractions do not go through LDS.  Known columns of F are used exactly: F[:,0..2] = e_0..e_2
 // (nothing depends on position), F[:,7..9] = dt e_0..2 + e_7..9 (velocity only
 // drives position), and rows 10..12 of F[:,3..6] are zero (body rates do not
 // depend on the attitude).
+// Fused row-broadcast FMAs.  gfx950 has v_fmac_f64 with a DPP row_newbcast
+// source (the broadcast operand read from one lane of the 16-lane row, then
+// multiplied and accumulated in FP64), but the compiler only emits 64-bit DPP
+// as two 32-bit DPP moves followed by the FMA.  These helpers issue the fused
+// form from inline asm, one block per group of independent updates.  DPP reads
+// need wait states after a VALU write of the source (and after an EXEC
+// write), which the compiler does not insert around inline asm; each block
+// therefore starts with s_nop 4 (five wait states), and inside a block no
+// instruction writes a DPP source (outputs are read-write operands, so they
+// cannot share a register with an input).  Accumulation order per output is
+// the order of the calls, as in the plain fma() form.
+// Y[i] += (V[i] of lane K) * f, i < 13
+template <int K>
+__device__ __forceinline__ void y_block(double (&Y)[NX], const double (&V)[NX], double f) {
+  asm("s_nop 4\n\tv_fmac_f64_dpp %0, %13, %26 row_newbcast:%27 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %1, %14, %26 row_newbcast:%27 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %2, %15, %26 row_newbcast:%27 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %3, %16, %26 row_newbcast:%27 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %4, %17, %26 row_newbcast:%27 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %5, %18, %26 row_newbcast:%27 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %6, %19, %26 row_newbcast:%27 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %7, %20, %26 row_newbcast:%27 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %8, %21, %26 row_newbcast:%27 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %9, %22, %26 row_newbcast:%27 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %10, %23, %26 row_newbcast:%27 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %11, %24, %26 row_newbcast:%27 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %12, %25, %26 row_newbcast:%27 row_mask:0xf bank_mask:0xf"
+      : "+v"(Y[0]), "+v"(Y[1]), "+v"(Y[2]), "+v"(Y[3]), "+v"(Y[4]), "+v"(Y[5]), "+v"(Y[6]), "+v"(Y[7]), "+v"(Y[8]), "+v"(Y[9]), "+v"(Y[10]), "+v"(Y[11]), "+v"(Y[12])
+      : "v"(V[0]), "v"(V[1]), "v"(V[2]), "v"(V[3]), "v"(V[4]), "v"(V[5]), "v"(V[6]), "v"(V[7]), "v"(V[8]), "v"(V[9]), "v"(V[10]), "v"(V[11]), "v"(V[12]), "v"(f), "n"(K));
+}
+
+// Q[i] += (f of lane lane_of(i)) * y for i in 3..6, 10..16 (one stage k < 10 of F^T Y)
+__device__ __forceinline__ void q_block_a(double (&Q)[NZ], double f, double y) {
+  asm("s_nop 4\n\tv_fmac_f64_dpp %0, %11, %12 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %1, %11, %12 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %2, %11, %12 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %3, %11, %12 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %4, %11, %12 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %5, %11, %12 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %6, %11, %12 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %7, %11, %12 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %8, %11, %12 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %9, %11, %12 row_newbcast:15 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %10, %11, %12 row_newbcast:0 row_mask:0xf bank_mask:0xf"
+      : "+v"(Q[3]), "+v"(Q[4]), "+v"(Q[5]), "+v"(Q[6]), "+v"(Q[10]), "+v"(Q[11]), "+v"(Q[12]), "+v"(Q[13]), "+v"(Q[14]), "+v"(Q[15]), "+v"(Q[16])
+      : "v"(f), "v"(y));
+}
+
+// Q[i] += (f of lane lane_of(i)) * y for i in 10..16 (stages k >= 10 of F^T Y)
+__device__ __forceinline__ void q_block_b(double (&Q)[NZ], double f, double y) {
+  asm("s_nop 4\n\tv_fmac_f64_dpp %0, %7, %8 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %1, %7, %8 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %2, %7, %8 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %3, %7, %8 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %4, %7, %8 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %5, %7, %8 row_newbcast:15 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %6, %7, %8 row_newbcast:0 row_mask:0xf bank_mask:0xf"
+      : "+v"(Q[10]), "+v"(Q[11]), "+v"(Q[12]), "+v"(Q[13]), "+v"(Q[14]), "+v"(Q[15]), "+v"(Q[16])
+      : "v"(f), "v"(y));
+}
+
+// S[j] += (k of lane j) * q for j < 13 (one control's term of the V update)
+__device__ __forceinline__ void v_block(double (&S)[NX], double k, double q) {
+  asm("s_nop 4\n\tv_fmac_f64_dpp %0, %13, %14 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %1, %13, %14 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %2, %13, %14 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %3, %13, %14 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %4, %13, %14 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %5, %13, %14 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %6, %13, %14 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %7, %13, %14 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %8, %13, %14 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %9, %13, %14 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %10, %13, %14 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %11, %13, %14 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %12, %13, %14 row_newbcast:12 row_mask:0xf bank_mask:0xf"
+      : "+v"(S[0]), "+v"(S[1]), "+v"(S[2]), "+v"(S[3]), "+v"(S[4]), "+v"(S[5]), "+v"(S[6]), "+v"(S[7]), "+v"(S[8]), "+v"(S[9]), "+v"(S[10]), "+v"(S[11]), "+v"(S[12])
+      : "v"(k), "v"(q));
+}
+
+// acc += sum_k (v of lane k) * F[k], k = 0..12 in order
+__device__ __forceinline__ void fv_chain(double& acc, double v, const double (&F)[NX]) {
+  asm("s_nop 4\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %0, %1, %3 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %0, %1, %4 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %0, %1, %5 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %0, %1, %6 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %0, %1, %7 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %0, %1, %8 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %0, %1, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %0, %1, %10 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %0, %1, %11 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %0, %1, %12 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %0, %1, %13 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\tv_fmac_f64_dpp %0, %1, %14 row_newbcast:12 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc)
+      : "v"(v), "v"(F[0]), "v"(F[1]), "v"(F[2]), "v"(F[3]), "v"(F[4]), "v"(F[5]), "v"(F[6]), "v"(F[7]), "v"(F[8]), "v"(F[9]), "v"(F[10]), "v"(F[11]), "v"(F[12]));
+}
+
+// B[j] = v of lane j, j < 16
+__device__ __forceinline__ void bcast16(double (&Bv)[16], double v) {
+  asm("s_nop 4\n\tv_mov_b64_dpp %0, %16 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %1, %16 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %2, %16 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %3, %16 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %4, %16 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %5, %16 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %6, %16 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %7, %16 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %8, %16 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %9, %16 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %10, %16 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %11, %16 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %12, %16 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %13, %16 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %14, %16 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %15, %16 row_newbcast:15 row_mask:0xf bank_mask:0xf"
+      : "=&v"(Bv[0]), "=&v"(Bv[1]), "=&v"(Bv[2]), "=&v"(Bv[3]), "=&v"(Bv[4]), "=&v"(Bv[5]), "=&v"(Bv[6]), "=&v"(Bv[7]), "=&v"(Bv[8]), "=&v"(Bv[9]), "=&v"(Bv[10]), "=&v"(Bv[11]), "=&v"(Bv[12]), "=&v"(Bv[13]), "=&v"(Bv[14]), "=&v"(Bv[15])
+      : "v"(v));
+}
+
+// the 4x4 control block Q[13+a][13+b] (upper triangle, column b from lane
+// lane_of(13+b): h[] in the order (0,0) (0,1) (1,1) (0,2) (1,2) (2,2) (0,3) ..)
+// and q_u[b] from the same lanes
+__device__ __forceinline__ void hq_block(double (&h)[10], double (&qu)[4], const double (&Qc)[NZ], double qc) {
+  asm("s_nop 4\n\tv_mov_b64_dpp %0, %14 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %1, %14 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %2, %15 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %3, %14 row_newbcast:15 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %4, %15 row_newbcast:15 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %5, %16 row_newbcast:15 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %6, %14 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %7, %15 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %8, %16 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %9, %17 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %10, %18 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %11, %18 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %12, %18 row_newbcast:15 row_mask:0xf bank_mask:0xf\n\tv_mov_b64_dpp %13, %18 row_newbcast:0 row_mask:0xf bank_mask:0xf"
+      : "=&v"(h[0]), "=&v"(h[1]), "=&v"(h[2]), "=&v"(h[3]), "=&v"(h[4]), "=&v"(h[5]), "=&v"(h[6]), "=&v"(h[7]), "=&v"(h[8]), "=&v"(h[9]), "=&v"(qu[0]), "=&v"(qu[1]), "=&v"(qu[2]), "=&v"(qu[3])
+      : "v"(Qc[13]), "v"(Qc[14]), "v"(Qc[15]), "v"(Qc[16]), "v"(qc));
+}
+
 // value of v in lane L of this lane's 16-lane row (L a compile-time constant)
 template <int L>
 __device__ __forceinline__ double bc(double v) {
@@ -220,6 +284,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
   if (vinit && l < NX) vl = vinit[CK_VV + l];
   float zn[NZ];
   if (t_hi > t_lo) load_z(traj_at(A, b, n, t_hi - 1), zn);
+  __builtin_amdgcn_s_waitcnt(0);  // no load pending on loop entry (see grp_ls)
   for (int t = t_hi - 1; t >= t_lo; --t) {
     if (MODE == 2 && t + 1 < T && (t + 1) % A.ckpt == 0) {
       // V, v of stage t + 1 (complete since the last row sync): exact FP64 image
@@ -231,6 +296,17 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
       }
     }
     const float* zp = traj_at(A, b, n, t);
+    // this stage's own scalars are loaded before the next stage's nominal: the
+    // vector-memory counter is in order, so they can then be waited for
+    // without also waiting for the prefetch
+    const size_t srow0 = (size_t)b * A.Tm + t;
+    const float s_zc = zp[col < NX ? col : col + 3];
+    const float s_qc = DENSE ? 0.f : A.Q[srow0 * NZ + col];
+    const float s_q0 = DENSE ? 0.f : A.Q[srow0 * NZ];
+    const float s_pc = A.p[srow0 * NZ + col];
+    const float s_p0 = A.p[srow0 * NZ];
+    float4 s_kw = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (MODE == 0 && kit > 0) s_kw = *(const float4*)(gains_at(A, b, t) + 64);
     float zb[NZ];
 #pragma unroll
     for (int i = 0; i < NZ; ++i) zb[i] = zn[i];
@@ -273,11 +349,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     double Yc[NX];
 #pragma unroll
     for (int i = 0; i < NX; ++i) Yc[i] = 0.0;
-    sfor<NX>([&](auto K) {
-      constexpr int k = K;
-#pragma unroll
-      for (int i = 0; i < NX; ++i) Yc[i] = fma(bc<k>(Vr[i]), Fd[k], Yc[i]);
-    });
+    sfor<NX>([&](auto K) { y_block<K>(Yc, Vr, Fd[K]); });
     // Q[:, col] = (F^T V F)[:, col]; column i of F comes from lane lane_of(i)
     double Qc[NZ];
     Qc[0] = Yc[0];
@@ -285,33 +357,26 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     Qc[2] = Yc[2];
 #pragma unroll
     for (int m = 0; m < 3; ++m) Qc[7 + m] = fma(hdt, Yc[m], Yc[7 + m]);
-    sfor<4>([&](auto I) {
-      constexpr int i = 3 + I;
-      double s = 0.0;
 #pragma unroll
-      for (int k = 0; k < 10; ++k) s = fma(bc<i>(Fd[k]), Yc[k], s);
-      Qc[i] = s;
-    });
-    sfor<7>([&](auto I) {
-      constexpr int i = 10 + I;
-      double s = 0.0;
+    for (int i = 3; i < 7; ++i) Qc[i] = 0.0;
 #pragma unroll
-      for (int k = 0; k < NX; ++k) s = fma(bc<lane_of(i)>(Fd[k]), Yc[k], s);
-      Qc[i] = s;
-    });
+    for (int i = 10; i < NZ; ++i) Qc[i] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) q_block_a(Qc, Fd[k], Yc[k]);
+#pragma unroll
+    for (int k = 10; k < NX; ++k) q_block_b(Qc, Fd[k], Yc[k]);
 
     // stage cost: Q += C_t, q = g + F^T v with g = C_t z + c_t
     const size_t srow = (size_t)b * A.Tm + t;
     const float* prow = A.p + srow * NZ;
     double qc, g0, c00;
     {
-      const double zb_c = (double)zp[col < NX ? col : col + 3];
+      const double zb_c = (double)s_zc;
       if (!DENSE) {
-        const float* qrow = A.Q + srow * NZ;
-        const double qd_c = (double)qrow[col];
-        c00 = (double)qrow[0];
-        qc = fma(qd_c, zb_c, (double)prow[col]);
-        g0 = fma(c00, (double)zb[0], (double)prow[0]);
+        const double qd_c = (double)s_qc;
+        c00 = (double)s_q0;
+        qc = fma(qd_c, zb_c, (double)s_pc);
+        g0 = fma(c00, (double)zb[0], (double)s_p0);
 #pragma unroll
         for (int i = 1; i < NZ; ++i) Qc[i] += (i == col) ? qd_c : 0.0;
       } else {
@@ -329,27 +394,26 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
         g0 = gz;
       }
     }
-    double vv[NX];
-    sfor<NX>([&](auto K) { vv[K] = bc<K>(vl); });
-#pragma unroll
-    for (int k = 0; k < NX; ++k) qc = fma(Fd[k], vv[k], qc);
-    const double q0 = g0 + vv[0];
+    fv_chain(qc, vl, Fd);
+    const double q0 = g0 + bc<0>(vl);
     const double v00 = bc<0>(Vr[0]);
     // control block and q_u from the lanes owning columns 13..16
     double H[16], qu[4];
-    sfor<4>([&](auto BB) {
-      constexpr int bb = BB;
+    {
+      double h[10];
+      hq_block(h, qu, Qc, qc);
+      int m = 0;
 #pragma unroll
-      for (int a = 0; a <= bb; ++a) {
-        const double h = bc<lane_of(13 + bb)>(Qc[13 + a]);
-        H[a * 4 + bb] = h;
-        H[bb * 4 + a] = h;
-      }
-      qu[bb] = bc<lane_of(13 + bb)>(qc);
-    });
+      for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int a = 0; a <= bb; ++a, ++m) {
+          H[a * 4 + bb] = h[m];
+          H[bb * 4 + a] = h[m];
+        }
+    }
     lds_write<NX>(L + L_QX + l * 14, Qc);
     double y0b[16];  // Y[0, :] by lane (row 0 of Q without the cost)
-    sfor<16>([&](auto J) { y0b[J] = bc<J>(Yc[0]); });
+    bcast16(y0b, Yc[0]);
     // row 0 of Q (lane 0's x-row; its own column is 16)
     auto R0 = [&](int j) -> double {
       double r = (j == 0) ? v00 + c00 : y0b[lane_of(j)];
@@ -368,10 +432,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     float* gp = gains_at(A, b, t);
     if (MODE == 0) {
       double kw[4] = {0.0, 0.0, 0.0, 0.0};
-      if (kit > 0) {
-        const float4 w = *(const float4*)(gp + 64);
-        kw[0] = w.x; kw[1] = w.y; kw[2] = w.z; kw[3] = w.w;
-      }
+      kw[0] = s_kw.x; kw[1] = s_kw.y; kw[2] = s_kw.z; kw[3] = s_kw.w;
       boxqp(H, qu, dl, dh, kw, A.piv, kv, fr, C, st);
     } else {
 #pragma unroll
@@ -406,11 +467,14 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
       double vi = (l == 0) ? q0 : qc;
 #pragma unroll
       for (int a = 0; a < 4; ++a) vi = fma(Qux[a], kv[a], vi);
+      double S[NX];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) S[j] = (l == 0) ? R0r[j] : L[L_QX + l * 14 + j];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) v_block(S, Kd[a], Qux[a]);
       sfor<NX>([&](auto J) {
         constexpr int j = J;
-        double s = (l == 0) ? R0r[j] : L[L_QX + l * 14 + j];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) s = fma(Qux[a], bc<j>(Kd[a]), s);
+        const double s = S[j];
         const int a1 = (j >= l) ? (L_V + l * 14 + j) : (L_DUM + l);
         const int a2 = (j > l) ? (L_V + j * 14 + l) : (L_DUM + l);
         L[a1] = s;
@@ -514,6 +578,11 @@ __device__ void grp_ls(const KArgs& A, const Grp& G, int n, float& Jout, float& 
   float J = 0.f, dm = 0.f;
   LsStage<DENSE> cur, nxt;
   if (T > 0) ls_load<DENSE>(A, b, n, 0, r, cur);
+  // Let the first stage's loads land before the loop: with loads still
+  // pending on entry, the wait counters inside the loop have to assume that
+  // any register could be one of them, and (the vector-memory counter being
+  // in order) the loop would wait on the next stage's prefetch at every stage.
+  __builtin_amdgcn_s_waitcnt(0);
   for (int t = 0; t < T; ++t) {
     if (t + 1 < T) ls_load<DENSE>(A, b, n, t + 1, r, nxt);
     float ur = cur.ub + alpha * cur.kr;
