@@ -908,84 +908,120 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
     grp_sweep<DENSE, 1, true>(A, G, n, 0, L, st, e, a, vinit, a);
     mem_fence_wg();
   };
-  double vrep[NX];
+  // backward vector sweep: q~ = d + F^T v, k~ = -M q~_u, v = q~_x + K^T q~_u.
+  // Each stage's factors are loaded one stage ahead (they do not depend on
+  // the recursion); lane l < 13 carries v_l.
+  struct VStage {
+    float fc[NX];
+    float dc, d0;
+    double M[16];
+    float4 kc;
+  };
+  auto vload = [&](int t, int a0, VStage& S) {
+    const float* tp = tail_at(A, b, CKPT ? t - a0 : t);
+    const size_t srow = (size_t)b * Tm + t;
+    S.dc = (col < NX) ? (A.gx ? A.gx[srow * NX + col] : 0.f) : A.gu[srow * NU + (col - NX)];
+    S.d0 = A.gx ? A.gx[srow * NX] : 0.f;
+    const float* fc = tp + col * 16;
+    const float4 f0 = *(const float4*)(fc), f1 = *(const float4*)(fc + 4), f2 = *(const float4*)(fc + 8);
+    S.fc[0] = f0.x; S.fc[1] = f0.y; S.fc[2] = f0.z; S.fc[3] = f0.w;
+    S.fc[4] = f1.x; S.fc[5] = f1.y; S.fc[6] = f1.z; S.fc[7] = f1.w;
+    S.fc[8] = f2.x; S.fc[9] = f2.y; S.fc[10] = f2.z; S.fc[11] = f2.w;
+    S.fc[12] = fc[12];
+    const double2* mp = (const double2*)(tp + FS + 52);
 #pragma unroll
-  for (int i = 0; i < NX; ++i) vrep[i] = 0.0;
+    for (int i = 0; i < 8; ++i) {
+      const double2 w = mp[i];
+      S.M[2 * i] = w.x;
+      S.M[2 * i + 1] = w.y;
+    }
+    S.kc = *(const float4*)(tp + FS + (l < NX ? l : 0) * 4);
+  };
   double vi = 0.0;
-  // backward vector sweep: q~ = d + F^T v, k~ = -M q~_u, v = q~_x + K^T q~_u
+  VStage cs, ns;
   for (int sg = nseg - 1; sg >= 0; --sg) {
     const int a = sg * seg, e = (a + seg < T) ? a + seg : T;
     if (CKPT) recompute(a, e);
+    vload(e - 1, a, cs);
+    __builtin_amdgcn_s_waitcnt(0);  // no load pending on loop entry (see grp_ls)
     for (int t = e - 1; t >= a; --t) {
-      const float* tp = tail_at(A, b, CKPT ? t - a : t);
+      if (t > a) vload(t - 1, a, ns);
       const size_t srow = (size_t)b * Tm + t;
-      const float d_c = (col < NX) ? (A.gx ? A.gx[srow * NX + col] : 0.f) : A.gu[srow * NU + (col - NX)];
-      const float d_0 = A.gx ? A.gx[srow * NX] : 0.f;
-      const float* fc = tp + col * 16;
-      double qc = (double)d_c;
+      double Fd[NX];
 #pragma unroll
-      for (int k = 0; k < NX; ++k) qc = fma((double)fc[k], vrep[k], qc);
-      const double q0 = (double)d_0 + vrep[0];
+      for (int k = 0; k < NX; ++k) Fd[k] = (double)cs.fc[k];
+      double qc = (double)cs.dc;
+      fv_chain(qc, vi, Fd);
+      const double q0 = (double)cs.d0 + bc<0>(vi);
       double qu[4];
 #pragma unroll
       for (int a4 = 0; a4 < 4; ++a4) qu[a4] = rb64(qc, lane_of(NX + a4));
-      const double* M = (const double*)(tp + FS + 52);
       double kt[4];
 #pragma unroll
       for (int a4 = 0; a4 < 4; ++a4) {
         double acc = 0.0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc = fma(M[a4 * 4 + c], qu[c], acc);
+        for (int c = 0; c < 4; ++c) acc = fma(cs.M[a4 * 4 + c], qu[c], acc);
         kt[a4] = -acc;
       }
       if (l == 0) *(float4*)(A.ws.ktil + srow * 4) = make_float4((float)kt[0], (float)kt[1], (float)kt[2], (float)kt[3]);
-      vi = (l == 0) ? q0 : qc;
-      if (l < NX) {
-        const float4 kc = *(const float4*)(tp + FS + l * 4);
-        vi = fma((double)kc.x, qu[0], vi);
-        vi = fma((double)kc.y, qu[1], vi);
-        vi = fma((double)kc.z, qu[2], vi);
-        vi = fma((double)kc.w, qu[3], vi);
-      } else {
-        vi = 0.0;
-      }
-#pragma unroll
-      for (int j = 0; j < NX; ++j) vrep[j] = rb64(vi, j);
+      double vn = (l == 0) ? q0 : qc;
+      vn = fma((double)cs.kc.x, qu[0], vn);
+      vn = fma((double)cs.kc.y, qu[1], vn);
+      vn = fma((double)cs.kc.z, qu[2], vn);
+      vn = fma((double)cs.kc.w, qu[3], vn);
+      vi = (l < NX) ? vn : 0.0;
+      if (t > a) cs = ns;
     }
   }
   if (l < NX) A.gx0[(size_t)b * NX + l] = (T > 0) ? (float)vi : 0.f;
-  mem_fence_wg();
+  mem_fence_wg();  // k~ written by lane 0 above is read by every lane below
   // forward sweep: u~ = K x~ + k~, x~' = A x~ + B u~;  dL/dc = z~, dL/dC from z~ and z*
+  struct FStage {
+    float4 kk;
+    float4 K[NX];
+    float zs[NZ];
+    float fr[NZ];
+  };
+  auto fload = [&](int t, int a0, FStage& S) {
+    const float* tp = tail_at(A, b, CKPT ? t - a0 : t);
+    const size_t srow = (size_t)b * Tm + t;
+    S.kk = *(const float4*)(A.ws.ktil + srow * 4);
+#pragma unroll
+    for (int j = 0; j < NX; ++j) S.K[j] = *(const float4*)(tp + FS + j * 4);
+    load_z(traj_at(A, b, n, t), S.zs);
+    // row l of F = [A | B]: column c stored at c * 16
+#pragma unroll
+    for (int c = 0; c < NZ; ++c) S.fr[c] = tp[c * 16 + (l < NX ? l : 0)];
+  };
   float xt[NX];
 #pragma unroll
   for (int i = 0; i < NX; ++i) xt[i] = 0.f;
+  FStage cf, nf;
   for (int sg = 0; sg < nseg; ++sg) {
     const int a = sg * seg, e = (a + seg < T) ? a + seg : T;
     if (CKPT) recompute(a, e);
+    fload(a, a, cf);
+    __builtin_amdgcn_s_waitcnt(0);  // no load pending on loop entry
     for (int t = a; t < e; ++t) {
+      if (t + 1 < e) fload(t + 1, a, nf);
       const size_t srow = (size_t)b * Tm + t;
-      const float* tp = tail_at(A, b, CKPT ? t - a : t);
-      const float4 kk = *(const float4*)(A.ws.ktil + srow * 4);
-      float ut[4] = {kk.x, kk.y, kk.z, kk.w};
+      float ut[4] = {cf.kk.x, cf.kk.y, cf.kk.z, cf.kk.w};
 #pragma unroll
       for (int j = 0; j < NX; ++j) {
-        const float4 kj = *(const float4*)(tp + FS + j * 4);
-        ut[0] = fmaf(kj.x, xt[j], ut[0]);
-        ut[1] = fmaf(kj.y, xt[j], ut[1]);
-        ut[2] = fmaf(kj.z, xt[j], ut[2]);
-        ut[3] = fmaf(kj.w, xt[j], ut[3]);
+        ut[0] = fmaf(cf.K[j].x, xt[j], ut[0]);
+        ut[1] = fmaf(cf.K[j].y, xt[j], ut[1]);
+        ut[2] = fmaf(cf.K[j].z, xt[j], ut[2]);
+        ut[3] = fmaf(cf.K[j].w, xt[j], ut[3]);
       }
-      float zs[NZ];
-      load_z(traj_at(A, b, n, t), zs);
       if (l == 0) {
         float* zt = zz[grp][0];
         float* zr = zz[grp][1];
         for (int i = 0; i < NX; ++i) zt[i] = xt[i];
         for (int a4 = 0; a4 < NU; ++a4) zt[NX + a4] = ut[a4];
-        for (int i = 0; i < NZ; ++i) zr[i] = zs[i];
+        for (int i = 0; i < NZ; ++i) zr[i] = cf.zs[i];
       }
-      mem_fence_wg();
-      __builtin_amdgcn_wave_barrier();
+      lds_sync();
       const float* zt = zz[grp][0];
       const float* zr = zz[grp][1];
       for (int ee = l; ee < NZ; ee += 16) A.gp[srow * NZ + ee] = zt[ee];
@@ -997,20 +1033,19 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
           A.gQ[srow * NPK + m] = (i == j) ? zt[i] * zr[i] : zt[i] * zr[j] + zt[j] * zr[i];
         }
       }
-      mem_fence_wg();
-      __builtin_amdgcn_wave_barrier();
+      lds_sync();
       if (t + 1 < T) {
         float xi = 0.f;
         if (l < NX) {
-          // row l of F = [A | B]: column c stored at c * 16
 #pragma unroll
-          for (int c = 0; c < NX; ++c) xi = fmaf(tp[c * 16 + l], xt[c], xi);
+          for (int c = 0; c < NX; ++c) xi = fmaf(cf.fr[c], xt[c], xi);
 #pragma unroll
-          for (int a4 = 0; a4 < NU; ++a4) xi = fmaf(tp[(NX + a4) * 16 + l], ut[a4], xi);
+          for (int a4 = 0; a4 < NU; ++a4) xi = fmaf(cf.fr[NX + a4], ut[a4], xi);
         }
 #pragma unroll
         for (int j = 0; j < NX; ++j) xt[j] = rb(xi, j);
       }
+      if (t + 1 < e) cf = nf;
     }
   }
   for (int t = T; t < Tm; ++t) {
