@@ -217,6 +217,80 @@ def latency_table(reps=20, warmup=3):
     return rows
 
 
+def closed_loop_latency(steps=40, warmup=5):
+    """Latency of one receding-horizon control step at B = 1 (forward solve
+    from the current state + apply u*_0 + shift), hover-to-target workload,
+    for T 10, 20, 50: fixed K = 5, and K <= 30 stopping at ||dU||_inf < 1e-5,
+    each cold (every solve from hover thrust) and warm (from the shifted
+    previous solution), the warm loop also as one captured HIP graph per step.
+    wall_ms: host time from the call to the step's completion (stream
+    synchronised); gpu_ms: HIP events around the step on its stream.  Each
+    variant runs twice, in the order cold, warm, graph and then reversed (so
+    that clock ramps do not favour one), `steps` timed steps of a running
+    closed loop after `warmup` steps each time; medians over both runs."""
+    import numpy as np
+    import torch
+
+    import paper_2605_29155_amd as D
+    import workloads as W
+    from paper_2605_29155_amd.receding import RecedingHorizon
+    dev = "cuda:0"
+    h = D.Handle(0)
+
+    def run(t, T, K, tol, warm, graph):
+        rh = RecedingHorizon(W.quad_params_f32(), 1, T, max_iter=K, tol_du=tol, warm=warm, handle=h)
+        rh.reset(t["x0"])
+        s = torch.cuda.Stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        wall, gpu, its = [], [], []
+        with torch.cuda.stream(s):
+            if graph:
+                rh.step(t["Q"], t["p"], t["lo"], t["hi"], stream=s)
+                s.synchronize()
+                rh.capture(t["Q"], t["p"], t["lo"], t["hi"], stream=s)
+            for r in range(warmup + steps):
+                s.synchronize()
+                c0 = time.perf_counter()
+                e0.record(s)
+                if graph:
+                    rh.replay()
+                else:
+                    rh.step(t["Q"], t["p"], t["lo"], t["hi"], stream=s)
+                e1.record(s)
+                s.synchronize()
+                c1 = time.perf_counter()
+                if r >= warmup:
+                    wall.append((c1 - c0) * 1e3)
+                    gpu.append(e0.elapsed_time(e1))
+                    its.append((int(rh.status.item()) >> 8) & 255)
+        rh.release()
+        return wall, gpu, its, rh.x[0, :3].cpu().numpy()
+
+    rows = []
+    variants = ((False, False), (True, False), (True, True))
+    for T in (10, 20, 50):
+        d = W.make_hover_target(1, T)
+        t = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev) for k in ("x0", "Q", "p", "lo", "hi")}
+        target = -d["p"][0, 0, :3] / d["Q"][0, 0, :3]
+        for K, tol in ((5, 0.0), (30, 1e-5)):
+            acc = {v: ([], [], [], None) for v in variants}
+            for v in variants + variants[::-1]:
+                w, g, i, pos = run(t, T, K, tol, *v)
+                acc[v] = (acc[v][0] + w, acc[v][1] + g, acc[v][2] + i, pos)
+            for (warm, graph) in variants:
+                w, g, i, pos = acc[(warm, graph)]
+                row = dict(B=1, T=T, K=K, tol_du=tol, warm=warm, graph=graph, wall_ms=float(np.median(w)),
+                           wall_ms_p90=float(np.percentile(w, 90)), gpu_ms=float(np.median(g)),
+                           mean_iters=float(np.mean(i)), median_iters=float(np.median(i)),
+                           final_pos_err_m=float(np.linalg.norm(pos - target)))
+                rows.append(row)
+                print("closed loop T=%2d K=%2d tol=%g %-10s: wall %.3f ms (p90 %.3f), gpu %.3f ms, iterations "
+                      "mean %.1f median %.0f" % (T, K, tol, ("warm" if warm else "cold") + ("+graph" if graph else ""),
+                                                 row["wall_ms"], row["wall_ms_p90"], row["gpu_ms"],
+                                                 row["mean_iters"], row["median_iters"]), file=sys.stderr, flush=True)
+    return rows
+
+
 def cpu_baseline_leg(d, gpu, nsample=64):
     """Oracle on the host: time fwd + Riccati-adjoint bwd of the full batch on
     all host cores, and check the kernel on a sample with its decisions
@@ -271,6 +345,9 @@ def main():
     ap.add_argument("--latency", action="store_true",
                     help="forward / backward latency at the paper's Table I shapes (B 1 and 256, T 2, 10, 50) "
                          "on a hover-to-target workload; prints one JSON line with the table")
+    ap.add_argument("--closed-loop", action="store_true",
+                    help="receding-horizon control-step latency at B=1 (T 10, 20, 50; fixed K=5 and K<=30 with "
+                         "tol 1e-5; cold, warm, warm+graph); prints one JSON line with the table")
     ap.add_argument("--profile-short", action="store_true",
                     help="for counter collection: two direct fwd+bwd calls of the persistent form, then a "
                          "256 MiB device copy whose FETCH_SIZE / WRITE_SIZE calibrate the HBM counters")
@@ -284,6 +361,10 @@ def main():
     if a.latency:
         print(json.dumps({"latency_table": latency_table(), "workload": "hover_to_random_target, K=5",
                           "paper_hardware": "NVIDIA RTX A6000 + Intel i9-13900K"}), flush=True)
+        return
+    if a.closed_loop:
+        print(json.dumps({"closed_loop_latency": closed_loop_latency(), "workload": "hover_to_random_target, B=1"}),
+              flush=True)
         return
     print("bench: building inputs (B=4096, T=20, MLP cost)", file=sys.stderr, flush=True)
     d, t = make_inputs(dev)

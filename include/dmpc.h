@@ -145,16 +145,20 @@ int dmpc_validate(const dmpc_config* cfg);
  * is invalid).  Host-only. */
 size_t dmpc_workspace_bytes(const dmpc_config* cfg);
 
-/* Forward solve (Alg. 2 inner loop).  Reads x0, Q, p, u_lo, u_hi, T; writes
- * u_out, x_out (may be NULL), status [B] (bits above, iterations in bits
- * 8..15) and, when decision_log is not NULL, the decisions taken.  The
+/* Forward solve (Alg. 2 inner loop).  Reads x0, Q, p, u_lo, u_hi, T and
+ * u_init; writes u_out, x_out (may be NULL), status [B] (bits above,
+ * iterations in bits 8..15) and, when decision_log is not NULL, the decisions
+ * taken.  u_init [B][T_max][4] is the initial control sequence U^0 of the
+ * first rollout (a warm start; each entry clamped into [u_lo, u_hi]); NULL
+ * starts from hover thrust m g / 4 per rotor, clamped.  u_init may alias
+ * u_out only if the caller does not need u_init afterwards.  The
  * workspace (>= dmpc_workspace_bytes(cfg) bytes, 256-byte aligned) keeps the
  * solution and, with DMPC_NEED_GRAD, the stage factors read by dmpc_backward;
  * it must not be reused before that backward has run. */
 int dmpc_forward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* x0, const float* Q,
-                 const float* p, const float* u_lo, const float* u_hi, const int32_t* T, float* u_out,
-                 float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes, uint8_t* decision_log,
-                 void* stream);
+                 const float* p, const float* u_lo, const float* u_hi, const int32_t* T, const float* u_init,
+                 float* u_out, float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes,
+                 uint8_t* decision_log, void* stream);
 
 /* Backward (Sec. IV after eq. (3)): given dL/du* [B][T_max][4] and
  * optionally dL/dx* [B][T_max][13] (NULL = zero), writes
@@ -188,9 +192,25 @@ int dmpc_last_launch_count(dmpc_handle h);
  * entry point it synchronises `stream` (it measures), so it cannot be
  * captured in a graph; call it once before capturing.  `chosen` may be NULL. */
 int dmpc_autotune(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* x0, const float* Q,
-                  const float* p, const float* u_lo, const float* u_hi, const int32_t* T, float* u_out,
-                  float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes, void* stream,
-                  dmpc_launch_choice* chosen);
+                  const float* p, const float* u_lo, const float* u_hi, const int32_t* T, const float* u_init,
+                  float* u_out, float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes,
+                  void* stream, dmpc_launch_choice* chosen);
+
+/* One receding-horizon step (Alg. 1, outer loop: the first control of each
+ * solve is applied, then the horizon moves on by one stage).  For every
+ * instance b with horizon T_b = T[b] (T_max when T is NULL):
+ *   u_applied[b] = u_star[b][0]                                 ([B][4], may be NULL)
+ *   x_state[b]  <- RK4 step of the model (eq. (1), step dyn.dt) from x_state[b]
+ *                  under u_star[b][0]                            ([B][13], in place)
+ *   u_warm[b][t] = u_star[b][min(t + 1, T_b - 1)] for t < T_b, 0 beyond
+ *                                                                ([B][T_max][4], may be NULL)
+ * u_warm is meant as the u_init of the next dmpc_forward and may be the same
+ * buffer as u_star.  An instance with T_b = 0 keeps its state and gets zero
+ * controls.  All pointers are device pointers; one kernel launch, no
+ * workspace, no synchronisation.  DMPC_EINVAL for a NULL handle, cfg, x_state
+ * or u_star (with B > 0) or non-positive mass, inertia or step. */
+int dmpc_mpc_step(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const int32_t* T, float* x_state,
+                  const float* u_star, float* u_warm, float* u_applied, void* stream);
 
 /* Store (set) or read (get) the launch choice for the shape of cfg, with
  * has_T != 0 for calls that pass a T array.  get returns DMPC_EINVAL when no

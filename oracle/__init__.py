@@ -197,3 +197,56 @@ def active_mask(u, lo, hi, T=None):
     if T is not None:
         m[np.arange(u.shape[1])[None, :] >= np.asarray(T)[:, None]] = 0
     return m
+
+
+def shift_warm_start(u, T=None):
+    """Initial controls U^0 of the next receding-horizon solve built from this
+    solve's U* (Alg. 1/2 outer loop with a shifted warm start): stage t takes
+    stage t + 1, the last stage of each horizon repeats, stages >= T_b are 0."""
+    u = np.asarray(u, np.float64)
+    B, Tm = u.shape[:2]
+    Tb = np.full(B, Tm) if T is None else np.asarray(T)
+    out = np.zeros_like(u)
+    for b in range(B):
+        for t in range(int(Tb[b])):
+            out[b, t] = u[b, min(t + 1, int(Tb[b]) - 1)]
+    return out
+
+
+def receding_horizon(P, x0, cost, lo, hi, steps, T=None, K=5, tol=0.0, warm=True, plant=None, affine=None):
+    """Closed-loop MPC (Alg. 1/2 outer loop, Sec. II): at each step solve the
+    horizon problem from the current state, apply the first control of the
+    solution to the plant, and repeat from the state reached.
+
+    cost: (Q, p) for a time-invariant cost, or a callable (step, x) -> (Q, p).
+    warm: start each solve after the first from the shifted previous solution
+    (shift_warm_start); otherwise every solve starts from hover thrust.
+    plant: callable (x [B,13], u [B,4]) -> x_next; default one RK4 step of
+    the quadrotor model per instance.  An instance with T_b = 0 keeps its
+    state and applies zero controls.
+    Returns dict(x [steps+1,B,13], u [steps,B,4], iters [steps,B],
+    status [steps,B], u_star [steps,B,T,4], x_star [steps,B,T,13])."""
+    x = _d(x0).copy()
+    B = x.shape[0]
+    Tb = None if T is None else np.asarray(T, np.int32)
+    xs, us, its, sts, ustar, xstar = [x.copy()], [], [], [], [], []
+    u_init = None
+    for k in range(steps):
+        Qk, pk = cost(k, x) if callable(cost) else cost
+        out = forward(P, x, Qk, pk, lo, hi, T=Tb, K=K, tol=tol, affine=affine, u_init=u_init)
+        u0 = out["u"][:, 0].copy()
+        live = np.ones(B, bool) if Tb is None else Tb > 0
+        if plant is not None:
+            xn = plant(x, u0)
+        else:
+            xn = np.stack([rk4(P, x[b], u0[b]) for b in range(B)])
+        x = np.where(live[:, None], xn, x)
+        u_init = shift_warm_start(out["u"], Tb) if warm else None
+        xs.append(x.copy())
+        us.append(u0)
+        its.append(out["iters"].copy())
+        sts.append(out["status"].copy())
+        ustar.append(out["u"].copy())
+        xstar.append(out["x"].copy())
+    return dict(x=np.array(xs), u=np.array(us), iters=np.array(its), status=np.array(sts), u_star=np.array(ustar),
+                x_star=np.array(xstar))

@@ -67,10 +67,11 @@ def lib():
         L.dmpc_validate.argtypes = [C.POINTER(Config)]
         L.dmpc_workspace_bytes.argtypes = [C.POINTER(Config)]
         L.dmpc_workspace_bytes.restype = sz
-        L.dmpc_forward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 9 + [vp, sz, vp, vp]
+        L.dmpc_forward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 10 + [vp, sz, vp, vp]
         L.dmpc_backward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 5 + [sz] + [vp] * 5 + [vp]
         L.dmpc_last_launch_count.argtypes = [vp]
-        L.dmpc_autotune.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 9 + [vp, sz, vp, C.POINTER(LaunchChoice)]
+        L.dmpc_autotune.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 10 + [vp, sz, vp, C.POINTER(LaunchChoice)]
+        L.dmpc_mpc_step.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 6
         L.dmpc_set_tuned.argtypes = [vp, C.POINTER(Config), i32, C.POINTER(LaunchChoice)]
         L.dmpc_get_tuned.argtypes = [vp, C.POINTER(Config), i32, C.POINTER(LaunchChoice)]
         L.dmpc_last_launch_choice.argtypes = [vp, C.POINTER(LaunchChoice)]
@@ -157,19 +158,21 @@ def alloc_workspace(cfg, device):
     return buf[off:off + n]
 
 
-def forward_raw(h, cfg, params, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, ws, dlog=None, stream=None):
+def forward_raw(h, cfg, params, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, ws, dlog=None, stream=None,
+                u_init=None):
+    """u_init: [B][T_max][4] warm start of the first rollout (None: hover)."""
     rc = lib().dmpc_forward(h._h, C.byref(cfg), params, _ptr(x0), _ptr(Q), _ptr(p), _ptr(u_lo), _ptr(u_hi), _ptr(T, "int32"),
-                            _ptr(u_out), _ptr(x_out), _ptr(status, "int32"), _ptr(ws, "uint8"),
+                            _ptr(u_init), _ptr(u_out), _ptr(x_out), _ptr(status, "int32"), _ptr(ws, "uint8"),
                             ws.numel() if ws is not None else 0, _ptr(dlog, "uint8"), _stream(stream))
     h.check(rc, "dmpc_forward")
 
 
-def autotune(h, cfg, params, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, ws, stream=None):
+def autotune(h, cfg, params, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, ws, stream=None, u_init=None):
     """Time every launch choice on these inputs and store the fastest on the
     handle for this shape (synchronises the stream).  Returns the choice."""
     c = LaunchChoice()
     rc = lib().dmpc_autotune(h._h, C.byref(cfg), params, _ptr(x0), _ptr(Q), _ptr(p), _ptr(u_lo), _ptr(u_hi),
-                             _ptr(T, "int32"), _ptr(u_out), _ptr(x_out), _ptr(status, "int32"), _ptr(ws, "uint8"),
+                             _ptr(T, "int32"), _ptr(u_init), _ptr(u_out), _ptr(x_out), _ptr(status, "int32"), _ptr(ws, "uint8"),
                              ws.numel(), _stream(stream), C.byref(c))
     h.check(rc, "dmpc_autotune")
     return c
@@ -189,6 +192,15 @@ def last_launch_choice(h):
     c = LaunchChoice()
     h.check(lib().dmpc_last_launch_choice(h._h, C.byref(c)), "dmpc_last_launch_choice")
     return c
+
+
+def mpc_step(h, cfg, params, T, x_state, u_star, u_warm=None, u_applied=None, stream=None):
+    """One receding-horizon step on the device: x_state <- RK4(x_state,
+    u_star[:, 0]) in place, u_applied <- u_star[:, 0], u_warm <- u_star
+    shifted by one stage (last stage repeated; may be u_star itself)."""
+    rc = lib().dmpc_mpc_step(h._h, C.byref(cfg), params, _ptr(T, "int32"), _ptr(x_state), _ptr(u_star),
+                             _ptr(u_warm), _ptr(u_applied), _stream(stream))
+    h.check(rc, "dmpc_mpc_step")
 
 
 def backward_raw(h, cfg, params, Q, p, u_lo, u_hi, ws, grad_u, grad_x, grad_Q, grad_p, grad_x0, stream=None):

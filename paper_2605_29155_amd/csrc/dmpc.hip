@@ -48,6 +48,7 @@ struct KArgs {
   int has_lin;             // the workspace holds the per-launch form's linearisation buffer
   float tol, piv;
   const float *x0, *Q, *p, *lo, *hi;
+  const float* uinit;  // [B][Tm][4] initial controls (warm start) or null (hover thrust)
   const int* T;
   float *u_out, *x_out;
   uint32_t* status;
@@ -120,14 +121,16 @@ __device__ __forceinline__ Grp make_grp(const KArgs& A, int slot, int l) {
   return G;
 }
 
-// initial nominal (Alg. 2, Rollout): U^0 = clamp(m g / 4), X^0 by RK4
+// initial nominal (Alg. 2, Rollout): U^0 = clamp(warm start, or m g / 4 without
+// one), X^0 by RK4
 __device__ void grp_init(const KArgs& A, const Grp& G) {
   float x[NX], xn[NX], u[NU];
 #pragma unroll
   for (int i = 0; i < NX; ++i) x[i] = A.x0[(size_t)G.b * NX + i];
-#pragma unroll
-  for (int a = 0; a < NU; ++a) u[a] = clampf(A.P.hover, G.lo[a], G.hi[a]);
   for (int t = 0; t < G.T; ++t) {
+    const float* ui = A.uinit ? A.uinit + ((size_t)G.b * A.Tm + t) * NU : nullptr;
+#pragma unroll
+    for (int a = 0; a < NU; ++a) u[a] = clampf(ui ? ui[a] : A.P.hover, G.lo[a], G.hi[a]);
     if (G.l == 0) store_z(traj_at(A, G.b, 0, t), x, u);
     if (t + 1 < G.T) {
       rk4(A.P, x, u, xn);
@@ -1056,6 +1059,47 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// receding horizon (Alg. 1 outer loop): apply u*_0 to the state with one RK4
+// step of the model, and shift the solution by one stage for the next solve's
+// warm start (the last stage repeats).  One thread per instance; u_warm may
+// be the same buffer as u_star (each thread reads stage t + 1 before it
+// writes stage t).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(64) void k_mpc_step(Dyn P, int B, int Tm, const int* Tarr, float* xs, const float* us,
+                                                 float* uw, float* ua) {
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  if (b >= B) return;
+  int T = Tarr ? Tarr[b] : Tm;
+  T = T < 0 ? 0 : (T > Tm ? Tm : T);
+  float u0[NU] = {0.f, 0.f, 0.f, 0.f};
+  if (T > 0) {
+#pragma unroll
+    for (int a = 0; a < NU; ++a) u0[a] = us[(size_t)b * Tm * NU + a];
+    float x[NX], xn[NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) x[i] = xs[(size_t)b * NX + i];
+    rk4(P, x, u0, xn);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) xs[(size_t)b * NX + i] = xn[i];
+  }
+  if (ua) {
+#pragma unroll
+    for (int a = 0; a < NU; ++a) ua[(size_t)b * NU + a] = u0[a];
+  }
+  if (uw) {
+    for (int t = 0; t < Tm; ++t) {
+      const int src = (t + 1 < T) ? t + 1 : T - 1;
+#pragma unroll
+      for (int a = 0; a < NU; ++a) {
+        const float v = (t < T) ? us[((size_t)b * Tm + src) * NU + a] : 0.f;
+        uw[((size_t)b * Tm + t) * NU + a] = v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 
@@ -1220,7 +1264,8 @@ dmpc_launch_choice default_choice(const dmpc_config* c) {
 }
 
 int forward_args(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* x0, const float* Q,
-                 const float* p, const float* u_lo, const float* u_hi, const int32_t* T, float* u_out,
+                 const float* p, const float* u_lo, const float* u_hi, const int32_t* T, const float* u_init,
+                 float* u_out,
                  float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes, uint8_t* decision_log,
                  KArgs& A) {
   if (!h) return fail(nullptr, DMPC_EINVAL, "NULL handle");
@@ -1245,6 +1290,7 @@ int forward_args(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, co
   A.lo = u_lo;
   A.hi = u_hi;
   A.T = T;
+  A.uinit = u_init;
   A.u_out = u_out;
   A.x_out = x_out;
   A.status = status;
@@ -1367,12 +1413,12 @@ const char* dmpc_last_error(dmpc_handle h) { return h ? h->err.c_str() : g_err.c
 int dmpc_last_launch_count(dmpc_handle h) { return h ? h->last_launches : -1; }
 
 int dmpc_forward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* x0, const float* Q,
-                 const float* p, const float* u_lo, const float* u_hi, const int32_t* T, float* u_out,
-                 float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes, uint8_t* decision_log,
-                 void* stream) {
+                 const float* p, const float* u_lo, const float* u_hi, const int32_t* T, const float* u_init,
+                 float* u_out, float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes,
+                 uint8_t* decision_log, void* stream) {
   KArgs A;
-  int rc = forward_args(h, cfg, dyn, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, workspace, workspace_bytes,
-                        decision_log, A);
+  int rc = forward_args(h, cfg, dyn, x0, Q, p, u_lo, u_hi, T, u_init, u_out, x_out, status, workspace,
+                        workspace_bytes, decision_log, A);
   if (rc || cfg->B == 0) return rc;
   dmpc_launch_choice c = default_choice(cfg);
   if (cfg->flags & DMPC_TUNED) {
@@ -1383,12 +1429,12 @@ int dmpc_forward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, co
 }
 
 int dmpc_autotune(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* x0, const float* Q,
-                  const float* p, const float* u_lo, const float* u_hi, const int32_t* T, float* u_out,
-                  float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes, void* stream,
-                  dmpc_launch_choice* chosen) {
+                  const float* p, const float* u_lo, const float* u_hi, const int32_t* T, const float* u_init,
+                  float* u_out, float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes,
+                  void* stream, dmpc_launch_choice* chosen) {
   KArgs A;
-  int rc = forward_args(h, cfg, dyn, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, workspace, workspace_bytes,
-                        nullptr, A);
+  int rc = forward_args(h, cfg, dyn, x0, Q, p, u_lo, u_hi, T, u_init, u_out, x_out, status, workspace,
+                        workspace_bytes, nullptr, A);
   if (rc) return rc;
   dmpc_launch_choice best = default_choice(cfg);
   best.ms = 0.f;
@@ -1507,6 +1553,24 @@ int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, c
     if (dense) k_bwd<true, false><<<A.nquads, 64, 0, s>>>(A);
     else k_bwd<false, false><<<A.nquads, 64, 0, s>>>(A);
   }
+  h->last_launches = 1;
+  return hip_check(h, hipGetLastError(), "kernel launch");
+}
+
+int dmpc_mpc_step(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const int32_t* T, float* x_state,
+                  const float* u_star, float* u_warm, float* u_applied, void* stream) {
+  if (!h) return fail(nullptr, DMPC_EINVAL, "NULL handle");
+  int rc = check_cfg(cfg);
+  if (rc) return fail(h, rc, "invalid configuration");
+  h->last_launches = 0;
+  if (cfg->B == 0) return DMPC_OK;
+  if (!x_state || !u_star) return fail(h, DMPC_EINVAL, "NULL required pointer");
+  if (!(dyn.mass > 0.f) || !(dyn.Jxx > 0.f) || !(dyn.Jyy > 0.f) || !(dyn.Jzz > 0.f) || !(dyn.dt > 0.f))
+    return fail(h, DMPC_EINVAL, "non-positive mass, inertia or step");
+  rc = hip_check(h, hipSetDevice(h->device), "hipSetDevice");
+  if (rc) return rc;
+  k_mpc_step<<<(cfg->B + 63) / 64, 64, 0, (hipStream_t)stream>>>(make_dyn(dyn), cfg->B, cfg->T_max, T, x_state,
+                                                                   u_star, u_warm, u_applied);
   h->last_launches = 1;
   return hip_check(h, hipGetLastError(), "kernel launch");
 }

@@ -64,8 +64,9 @@ def test_calls_without_handle_fail_cleanly(D):
     L = D.lib()
     cfg = D.make_config(8, 10)
     p = D.QuadParams(0.75, 2.5e-3, 2.5e-3, 4.5e-3, 0.15, 0.01, 0.05, 9.81)
-    rc = L.dmpc_forward(None, C.byref(cfg), p, *([None] * 9), None, 0, None, None)
+    rc = L.dmpc_forward(None, C.byref(cfg), p, *([None] * 10), None, 0, None, None)
     assert rc == -1
+    assert L.dmpc_mpc_step(None, C.byref(cfg), p, None, None, None, None, None, None) == -1
     rc = L.dmpc_backward(None, C.byref(cfg), D.QuadParams(), None, None, None, None, None, 0, None, None, None, None,
                          None, None)
     assert rc == -1
@@ -106,7 +107,7 @@ def test_tuner_entry_points_host_checks(D):
     assert L.dmpc_get_tuned(None, C.byref(cfg), 1, C.byref(c)) == -1
     assert L.dmpc_last_launch_choice(None, C.byref(c)) == -1
     rc = L.dmpc_autotune(None, C.byref(cfg), D.QuadParams(), None, None, None, None, None, None, None, None, None,
-                         None, 0, None, None)
+                         None, None, 0, None, None)
     assert rc == -1
 
 

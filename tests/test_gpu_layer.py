@@ -118,12 +118,12 @@ def test_error_codes():
     L = D.lib()
     s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
     ptr = lambda a: None if a is None else C.c_void_p(a.data_ptr())  # noqa: E731
-    rc = L.dmpc_forward(h._h, C.byref(cfg), par, ptr(x0), ptr(Q), ptr(p), ptr(lo), ptr(hi), None, ptr(u), None,
-                        ptr(st), ptr(small), small.numel(), None, s)
+    rc = L.dmpc_forward(h._h, C.byref(cfg), par, ptr(x0), ptr(Q), ptr(p), ptr(lo), ptr(hi), None, None, ptr(u),
+                        None, ptr(st), ptr(small), small.numel(), None, s)
     assert rc == -4
     ws = D.alloc_workspace(cfg, dev)
-    rc = L.dmpc_forward(h._h, C.byref(cfg), par, None, ptr(Q), ptr(p), ptr(lo), ptr(hi), None, ptr(u), None,
-                        ptr(st), ptr(ws), n, None, s)
+    rc = L.dmpc_forward(h._h, C.byref(cfg), par, None, ptr(Q), ptr(p), ptr(lo), ptr(hi), None, None, ptr(u),
+                        None, ptr(st), ptr(ws), n, None, s)
     assert rc == -1
     rc = L.dmpc_backward(h._h, C.byref(cfg), par, None, None, None, None, ptr(ws), n, ptr(u), None, ptr(Q), ptr(p),
                          ptr(x0), s)
@@ -138,8 +138,8 @@ def test_error_codes():
     assert D.validate(D.make_config(8, 10, 0, 5, 0.0, 0, ckpt_every=-1)) == -1
     # B = 0: nothing to do, no launches
     z = D.make_config(0, 10)
-    rc = L.dmpc_forward(h._h, C.byref(z), par, None, None, None, None, None, None, None, None, None, None, 0,
-                        None, s)
+    rc = L.dmpc_forward(h._h, C.byref(z), par, None, None, None, None, None, None, None, None, None, None, None,
+                        0, None, s)
     assert rc == 0 and h.launch_count() == 0
     torch.cuda.synchronize()
 
