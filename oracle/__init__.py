@@ -14,7 +14,8 @@ import numpy as np
 
 from . import build as _build
 
-NX, NU, NZ, NPACK, NALPHA = 13, 4, 17, 153, 4
+NX, NU, NZ, NPACK, NALPHA, NTHETA = 13, 4, 17, 153, 4, 8
+THETA_NAMES = ("mass", "Jxx", "Jyy", "Jzz", "arm", "kappa", "dt", "g")
 COST_DIAG, COST_PACKED, COST_FULL = 0, 1, 2
 DYN_QUAD, DYN_AFFINE = 0, 1
 ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_QPFAIL, ST_REGULARIZED = 0x1, 0x2, 0x4, 0x10, 0x20
@@ -159,9 +160,10 @@ def forward(P, x0, Q, p, lo, hi, T=None, K=5, tol=0.0, affine=None, u_init=None,
 
 
 def backward(P, x0, Q, p, lo, hi, u_star, x_star, grad_u, grad_x=None, T=None, mask=None, method=0,
-             affine=None, nthreads=None):
+             affine=None, nthreads=None, dtheta=False):
     """Implicit-KKT gradients at (x*, u*).  method 0 = Riccati adjoint,
-    1 = dense KKT.  Returns dict(dQ, dp, dx0)."""
+    1 = dense KKT.  Returns dict(dQ, dp, dx0), plus dtheta [B, 8] (dL/d of
+    mass, Jxx, Jyy, Jzz, arm, kappa, dt, g) when dtheta is True."""
     x0, p, lo, hi = _d(x0), _d(p), _d(lo), _d(hi)
     Q = _d(Q)
     B, Tm = p.shape[0], p.shape[1]
@@ -176,10 +178,13 @@ def backward(P, x0, Q, p, lo, hi, u_star, x_star, grad_u, grad_x=None, T=None, m
     m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
     gx = None if grad_x is None else _d(grad_x)
     out = dict(dQ=np.zeros_like(Q), dp=np.zeros((B, Tm, NZ)), dx0=np.zeros((B, NX)))
+    if dtheta:
+        out["dtheta"] = np.zeros((B, NTHETA))
     rc = lib().orc_backward(
         C.byref(cfg), C.byref(P), _ptr(x0), _ptr(Q), _ptr(p), _ptr(lo), _ptr(hi), _ptr(Tarr, C.c_int32),
         _ptr(Aff), _ptr(Bff), _ptr(rff), _ptr(_d(u_star)), _ptr(_d(x_star)), _ptr(m, C.c_uint8),
-        _ptr(_d(grad_u)), _ptr(gx), C.c_int32(method), _ptr(out["dQ"]), _ptr(out["dp"]), _ptr(out["dx0"]))
+        _ptr(_d(grad_u)), _ptr(gx), C.c_int32(method), _ptr(out["dQ"]), _ptr(out["dp"]), _ptr(out["dx0"]),
+        _ptr(out.get("dtheta")))
     if rc != 0:
         raise ValueError("orc_backward failed (bad arguments or singular KKT system)")
     return out

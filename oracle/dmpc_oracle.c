@@ -46,17 +46,41 @@
 #define NU ORC_NU
 #define NZ ORC_NZ
 
+/* model constants as complex numbers: the complex step in one of them gives
+ * the derivative with respect to it (dynamics-parameter gradients) */
+typedef struct {
+  double _Complex mass, Jxx, Jyy, Jzz, arm, kappa, dt, g;
+} orc_params_cx;
+
 /* real instantiation of the dynamics */
 #define SC double
+#define PT orc_params
+#define PSC double
 #define FN(n) n##_r
 #include "dyn_impl.inc"
 #undef SC
+#undef PT
+#undef PSC
 #undef FN
-/* complex instantiation, for the complex-step derivative */
+/* complex states, real constants: the complex step in (x, u) */
 #define SC double _Complex
+#define PT orc_params
+#define PSC double
 #define FN(n) n##_c
 #include "dyn_impl.inc"
 #undef SC
+#undef PT
+#undef PSC
+#undef FN
+/* complex states and constants: the complex step in a model constant */
+#define SC double _Complex
+#define PT orc_params_cx
+#define PSC double _Complex
+#define FN(n) n##_p
+#include "dyn_impl.inc"
+#undef SC
+#undef PT
+#undef PSC
 #undef FN
 
 static const double kAlphas[ORC_NALPHA] = {1.0, 0.5, 0.25, 0.1};
@@ -79,101 +103,12 @@ void orc_rk4_complex_step(const orc_params* P, const double* x, const double* u,
   for (i = 0; i < NX; ++i) out[i] = cimag(yc[i]) / h;
 }
 
-/* Analytic partial derivatives of the right-hand side F(x, u). */
 void orc_dyn_jac(const orc_params* P, const double* x, const double* u, double* Fx, double* Fu) {
-  const double a = P->arm / sqrt(2.0);
-  const double qw = x[3], qx = x[4], qy = x[5], qz = x[6];
-  const double wx = x[10], wy = x[11], wz = x[12];
-  const double s = (u[0] + u[1] + u[2] + u[3]) / P->mass;
-  int j;
-  memset(Fx, 0, sizeof(double) * NX * NX);
-  memset(Fu, 0, sizeof(double) * NX * NU);
-  /* p' = v */
-  Fx[0 * NX + 7] = 1.0;
-  Fx[1 * NX + 8] = 1.0;
-  Fx[2 * NX + 9] = 1.0;
-  /* q' = 1/2 Omega(w) q */
-  {
-    const double Om[4][4] = {{0, -wx, -wy, -wz}, {wx, 0, wz, -wy}, {wy, -wz, 0, wx}, {wz, wy, -wx, 0}};
-    int r, c;
-    for (r = 0; r < 4; ++r)
-      for (c = 0; c < 4; ++c) Fx[(3 + r) * NX + 3 + c] = 0.5 * Om[r][c];
-  }
-  /* q' = 1/2 Xi(q) w */
-  {
-    const double Xi[4][3] = {{-qx, -qy, -qz}, {qw, -qz, qy}, {qz, qw, -qx}, {-qy, qx, qw}};
-    int r, c;
-    for (r = 0; r < 4; ++r)
-      for (c = 0; c < 3; ++c) Fx[(3 + r) * NX + 10 + c] = 0.5 * Xi[r][c];
-  }
-  /* v' = s b3(q) - g e3 */
-  Fx[7 * NX + 3] = s * 2.0 * qy;
-  Fx[7 * NX + 4] = s * 2.0 * qz;
-  Fx[7 * NX + 5] = s * 2.0 * qw;
-  Fx[7 * NX + 6] = s * 2.0 * qx;
-  Fx[8 * NX + 3] = -s * 2.0 * qx;
-  Fx[8 * NX + 4] = -s * 2.0 * qw;
-  Fx[8 * NX + 5] = s * 2.0 * qz;
-  Fx[8 * NX + 6] = s * 2.0 * qy;
-  Fx[9 * NX + 4] = -s * 4.0 * qx;
-  Fx[9 * NX + 5] = -s * 4.0 * qy;
-  /* w' = J^{-1}(tau - w x J w) */
-  Fx[10 * NX + 11] = -(P->Jzz - P->Jyy) * wz / P->Jxx;
-  Fx[10 * NX + 12] = -(P->Jzz - P->Jyy) * wy / P->Jxx;
-  Fx[11 * NX + 10] = -(P->Jxx - P->Jzz) * wz / P->Jyy;
-  Fx[11 * NX + 12] = -(P->Jxx - P->Jzz) * wx / P->Jyy;
-  Fx[12 * NX + 10] = -(P->Jyy - P->Jxx) * wy / P->Jzz;
-  Fx[12 * NX + 11] = -(P->Jyy - P->Jxx) * wx / P->Jzz;
-  /* inputs */
-  {
-    const double b3[3] = {2.0 * (qx * qz + qw * qy), 2.0 * (qy * qz - qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)};
-    const double mx[4] = {1, 1, -1, -1}, my[4] = {-1, 1, 1, -1}, mz[4] = {1, -1, 1, -1};
-    for (j = 0; j < NU; ++j) {
-      Fu[7 * NU + j] = b3[0] / P->mass;
-      Fu[8 * NU + j] = b3[1] / P->mass;
-      Fu[9 * NU + j] = b3[2] / P->mass;
-      Fu[10 * NU + j] = a * mx[j] / P->Jxx;
-      Fu[11 * NU + j] = a * my[j] / P->Jyy;
-      Fu[12 * NU + j] = P->kappa * mz[j] / P->Jzz;
-    }
-  }
+  dyn_jac_r(P, x, u, Fx, Fu);
 }
 
-/* Exact derivative of the RK4 map by the chain rule through the four stages:
- *   M_1 = [Fx | Fu](x_1),
- *   M_s = Fx(x_s) ([I | 0] + c_s dt M_{s-1}) + [0 | Fu(x_s)],  c = (1/2, 1/2, 1)
- *   [A | B] = [I | 0] + dt/6 (M_1 + 2 M_2 + 2 M_3 + M_4). */
 void orc_rk4_jac(const orc_params* P, const double* x, const double* u, double* A, double* B) {
-  static const double cst[4] = {0.0, 0.5, 0.5, 1.0};
-  static const double wgt[4] = {1.0, 2.0, 2.0, 1.0};
-  const double h = P->dt;
-  double M[NX * NZ], Mprev[NX * NZ], E[NX * NZ], S[NX * NZ];
-  double Fx[NX * NX], Fu[NX * NU], k[NX], xs[NX];
-  int s, i, j, l;
-  memset(S, 0, sizeof S);
-  memset(Mprev, 0, sizeof Mprev);
-  for (i = 0; i < NX; ++i) k[i] = 0.0;
-  for (s = 0; s < 4; ++s) {
-    /* stage point and d(stage point)/d(x,u) */
-    for (i = 0; i < NX; ++i) xs[i] = x[i] + cst[s] * h * k[i];
-    for (i = 0; i < NX; ++i)
-      for (j = 0; j < NZ; ++j) E[i * NZ + j] = (i == j ? 1.0 : 0.0) + cst[s] * h * Mprev[i * NZ + j];
-    dyn_r(P, xs, u, k);
-    orc_dyn_jac(P, xs, u, Fx, Fu);
-    for (i = 0; i < NX; ++i)
-      for (j = 0; j < NZ; ++j) {
-        double acc = 0.0;
-        for (l = 0; l < NX; ++l) acc += Fx[i * NX + l] * E[l * NZ + j];
-        if (j >= NX) acc += Fu[i * NU + (j - NX)];
-        M[i * NZ + j] = acc;
-      }
-    for (i = 0; i < NX * NZ; ++i) S[i] += wgt[s] * M[i];
-    memcpy(Mprev, M, sizeof M);
-  }
-  for (i = 0; i < NX; ++i) {
-    for (j = 0; j < NX; ++j) A[i * NX + j] = (i == j ? 1.0 : 0.0) + h / 6.0 * S[i * NZ + j];
-    for (j = 0; j < NU; ++j) B[i * NU + j] = h / 6.0 * S[i * NZ + NX + j];
-  }
+  rk4_jac_r(P, x, u, A, B);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -823,6 +758,86 @@ static int bwd_kkt_one(const inst_t* in, const double* Xs, const double* Us, con
   return rc;
 }
 
+/* The model constants with the imaginary step ih added to the j-th one
+ * (order of orc_params: mass, Jxx, Jyy, Jzz, arm, kappa, dt, g). */
+static void params_step(const orc_params* P, int j, double h, orc_params_cx* Pc) {
+  const double _Complex ih = h * _Complex_I;
+  Pc->mass = P->mass + (j == 0 ? ih : 0.0);
+  Pc->Jxx = P->Jxx + (j == 1 ? ih : 0.0);
+  Pc->Jyy = P->Jyy + (j == 2 ? ih : 0.0);
+  Pc->Jzz = P->Jzz + (j == 3 ? ih : 0.0);
+  Pc->arm = P->arm + (j == 4 ? ih : 0.0);
+  Pc->kappa = P->kappa + (j == 5 ? ih : 0.0);
+  Pc->dt = P->dt + (j == 6 ? ih : 0.0);
+  Pc->g = P->g + (j == 7 ? ih : 0.0);
+}
+
+/* Gradient with respect to the model constants theta.  The backward
+ * differentiates the LQ problem of the model linearised at the solution,
+ * x_{t+1} = F_t z_t + f_t with F_t = df/dz(z*_t; theta) and
+ * f_t = f(z*_t; theta) - F_t z*_t.  Amos et al.'s gradients with respect to
+ * F_t and f_t, carried to theta by the chain rule, give
+ *   dL/dtheta = sum_{t < T-1}  lt_{t+1}^T df/dtheta(z*_t) + ls_{t+1}^T d(F_t zt_t)/dtheta,
+ * where zt = dL/dc is the adjoint LQ solution and lt, ls are the costates of
+ * the adjoint solution and of the solution itself:
+ *   lt_t = (C_t zt_t + d_t)_x + A_t^T lt_{t+1},   ls_t = (C_t z*_t + c_t)_x + A_t^T ls_{t+1},
+ * with l_T = 0 (d = dL/dz*).  df/dtheta and d(F zt)/dtheta come from the
+ * complex step in each constant, through the RK4 map and its exact Jacobian. */
+static void theta_grad_one(const inst_t* in, const double* Xs, const double* Us, const double* zt, const double* d,
+                           double* dth) {
+  const int T = in->T;
+  const double h = 1e-30;
+  double lt[NX], ls[NX], nt[NX], ns[NX], A[NX * NX], B[NX * NU];
+  int t, i, j, k;
+  for (j = 0; j < ORC_NTHETA; ++j) dth[j] = 0.0;
+  memset(lt, 0, sizeof lt);
+  memset(ls, 0, sizeof ls);
+  for (t = T - 1; t >= 0; --t) {
+    const double* C = in->C + (size_t)t * NZ * NZ;
+    double zs[NZ];
+    for (i = 0; i < NX; ++i) zs[i] = Xs[t * NX + i];
+    for (i = 0; i < NU; ++i) zs[NX + i] = Us[t * NU + i];
+    if (t + 1 < T) {
+      /* lt, ls hold l_{t+1} here */
+      double _Complex xc[NX], uc[NU], yc[NX], Ac[NX * NX], Bc[NX * NU];
+      for (i = 0; i < NX; ++i) xc[i] = zs[i];
+      for (i = 0; i < NU; ++i) uc[i] = zs[NX + i];
+      for (j = 0; j < ORC_NTHETA; ++j) {
+        orc_params_cx Pc;
+        double acc = 0.0;
+        params_step(in->P, j, h, &Pc);
+        rk4_p(&Pc, xc, uc, yc);
+        rk4_jac_p(&Pc, xc, uc, Ac, Bc);
+        for (i = 0; i < NX; ++i) {
+          double _Complex fz = 0.0;
+          for (k = 0; k < NX; ++k) fz += Ac[i * NX + k] * zt[t * NZ + k];
+          for (k = 0; k < NU; ++k) fz += Bc[i * NU + k] * zt[t * NZ + NX + k];
+          acc += lt[i] * (cimag(yc[i]) / h) + ls[i] * (cimag(fz) / h);
+        }
+        dth[j] += acc;
+      }
+      orc_rk4_jac(in->P, zs, zs + NX, A, B);
+    }
+    /* costates of stage t */
+    for (i = 0; i < NX; ++i) {
+      double gt = d[t * NZ + i], gs = in->c[t * NZ + i];
+      for (k = 0; k < NZ; ++k) {
+        gt += C[i * NZ + k] * zt[t * NZ + k];
+        gs += C[i * NZ + k] * zs[k];
+      }
+      if (t + 1 < T)
+        for (k = 0; k < NX; ++k) {
+          gt += A[k * NX + i] * lt[k];
+          gs += A[k * NX + i] * ls[k];
+        }
+      nt[i] = gt;
+      ns[i] = gs;
+    }
+    memcpy(lt, nt, sizeof lt);
+    memcpy(ls, ns, sizeof ls);
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* batched drivers                                                          */
 /* ------------------------------------------------------------------------ */
@@ -843,7 +858,7 @@ typedef struct {
   const double *u_star, *x_star, *grad_u, *grad_x;
   const uint8_t* mask;
   int32_t method;
-  double *dQ, *dp, *dx0;
+  double *dQ, *dp, *dx0, *dtheta;
   int rc;
   /* partition */
   int b0, b1;
@@ -953,6 +968,13 @@ static void* bwd_worker(void* arg) {
       }
     }
     if (jb->dx0) memcpy(jb->dx0 + (size_t)b * NX, g0, sizeof g0);
+    if (jb->dtheta) {
+      double* o = jb->dtheta + (size_t)b * ORC_NTHETA;
+      if (in.T > 0)
+        theta_grad_one(&in, Xs, Us, zt, d, o);
+      else
+        for (i = 0; i < ORC_NTHETA; ++i) o[i] = 0.0;
+    }
     if (dpb) {
       memset(dpb, 0, sizeof(double) * Tm * NZ);
       memcpy(dpb, zt, sizeof(double) * in.T * NZ);
@@ -1061,10 +1083,11 @@ int orc_backward(const orc_config* cfg, const orc_params* P, const double* x0, c
                  const double* p, const double* lo, const double* hi, const int32_t* T,
                  const double* Aff, const double* Bff, const double* rff, const double* u_star,
                  const double* x_star, const uint8_t* mask, const double* grad_u, const double* grad_x,
-                 int32_t method, double* dQ, double* dp, double* dx0) {
+                 int32_t method, double* dQ, double* dp, double* dx0, double* dtheta) {
   job_t jb;
   if (check_cfg(cfg) || !u_star || !x_star || !grad_u) return -1;
   if (cfg->dyn_kind == ORC_DYN_AFFINE && (!Aff || !Bff || !rff)) return -1;
+  if (cfg->dyn_kind == ORC_DYN_AFFINE && dtheta) return -1; /* no model constants */
   memset(&jb, 0, sizeof jb);
   jb.cfg = cfg;
   jb.P = P;
@@ -1086,5 +1109,6 @@ int orc_backward(const orc_config* cfg, const orc_params* P, const double* x0, c
   jb.dQ = dQ;
   jb.dp = dp;
   jb.dx0 = dx0;
+  jb.dtheta = dtheta;
   return run_jobs(&jb, bwd_worker);
 }

@@ -64,6 +64,7 @@ extern "C" {
 #define ORC_UPPER 2
 
 #define ORC_ALPHA_NONE 255 /* line search found no finite candidate */
+#define ORC_NTHETA 8       /* model constants: the fields of orc_params, in order */
 
 typedef struct {
   double mass, Jxx, Jyy, Jzz, arm, kappa, dt, g;
@@ -131,14 +132,14 @@ int orc_forward(const orc_config* cfg, const orc_params* P, const double* x0, co
  *   exact equality with lo/hi.
  * grad_u [B][T_max][4] = dL/du*, grad_x [B][T_max][13] = dL/dx* or NULL.
  * Outputs: dQ [B][T_max][17|153|289] (layout of Q), dp [B][T_max][17],
- *   dx0 [B][13]; lam0 [B][13] or NULL receives -nu_0 (method 1) / v_0
- *   (method 0), i.e. dx0 again, for cross-checks.
+ *   dx0 [B][13]; dtheta [B][8] or NULL: dL/d(mass, Jxx, Jyy, Jzz, arm, kappa,
+ *   dt, g) through the linearised dynamics (quadrotor only; -1 with affine).
  */
 int orc_backward(const orc_config* cfg, const orc_params* P, const double* x0, const double* Q,
                  const double* p, const double* lo, const double* hi, const int32_t* T,
                  const double* Aff, const double* Bff, const double* rff, const double* u_star,
                  const double* x_star, const uint8_t* mask, const double* grad_u, const double* grad_x,
-                 int32_t method, double* dQ, double* dp, double* dx0);
+                 int32_t method, double* dQ, double* dp, double* dx0, double* dtheta);
 
 #ifdef __cplusplus
 }

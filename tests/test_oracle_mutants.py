@@ -19,8 +19,8 @@ MUTANTS = [
      "s += K[a * NX + i] * QuuK[a * NX + j] + 0.0 * Qux[a * NX + j] +"),
     ("sign_v_update", SRC, "s += K[a * NX + i] * Quuk[a] + K[a * NX + i] * q[NX + a] + Qux[a * NX + i] * k[a];",
      "s += K[a * NX + i] * Quuk[a] - K[a * NX + i] * q[NX + a] + Qux[a * NX + i] * k[a];"),
-    ("jac_b3y_sign", SRC, "Fx[8 * NX + 3] = -s * 2.0 * qx;", "Fx[8 * NX + 3] = s * 2.0 * qx;"),
-    ("rk4_jac_weights", SRC, "static const double wgt[4] = {1.0, 2.0, 2.0, 1.0};",
+    ("jac_b3y_sign", INC, "Fx[8 * 13 + 3] = -s * 2.0 * qx;", "Fx[8 * 13 + 3] = s * 2.0 * qx;"),
+    ("rk4_jac_weights", INC, "static const double wgt[4] = {1.0, 2.0, 2.0, 1.0};",
      "static const double wgt[4] = {1.0, 2.0, 1.0, 2.0};"),
     ("transposed_Atv", SRC, "for (l = 0; l < NX; ++l) s += F[l * NZ + i] * v[l];",
      "for (l = 0; l < NX; ++l) s += (i < NX ? F[i * NZ + l] : F[l * NZ + i]) * v[l];"),
@@ -35,6 +35,12 @@ MUTANTS = [
      "xd[4] = 0.5 * (qw * wx - qy * wz + qz * wy);"),
     ("boxqp_dual_sign", SRC, "if (!(g[i] >= -rel * mag)) ok = 0;", "if (!(g[i] <= rel * mag)) ok = 0;"),
     ("packed_grad_no_symmetrisation", SRC, ": zz[i] * zs[j] + zz[j] * zs[i];", ": zz[i] * zs[j];"),
+    ("theta_drops_solution_costate_term", SRC, "acc += lt[i] * (cimag(yc[i]) / h) + ls[i] * (cimag(fz) / h);",
+     "acc += lt[i] * (cimag(yc[i]) / h);"),
+    ("theta_adjoint_costate_sign", SRC, "gt += A[k * NX + i] * lt[k];", "gt -= A[k * NX + i] * lt[k];"),
+    ("theta_solution_costate_transposed", SRC, "gs += A[k * NX + i] * ls[k];", "gs += A[i * NX + k] * ls[k];"),
+    ("theta_zt_stage_index", SRC, "for (k = 0; k < NX; ++k) fz += Ac[i * NX + k] * zt[t * NZ + k];",
+     "for (k = 0; k < NX; ++k) fz += Ac[i * NX + k] * zt[(t + 1) * NZ + k];"),
 ]
 
 
@@ -53,7 +59,7 @@ def test_pins_catch_mutant(name, path, orig, mut):
                         os.path.join(td, "dmpc_oracle.c"), "-lm", "-lpthread"], check=True)
         env = dict(os.environ, DMPC_ORACLE_LIB=lib)
         pins = ["tests/test_oracle_dynamics.py", "tests/test_oracle_boxqp.py", "tests/test_oracle_lqr.py",
-                "tests/test_oracle_grad.py"]
+                "tests/test_oracle_grad.py", "tests/test_oracle_theta.py"]
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"] + pins,
                            cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
         assert r.returncode != 0, "pins did not catch mutant " + name
