@@ -168,14 +168,20 @@ int dmpc_forward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, co
  * preceding dmpc_forward, which must have had DMPC_NEED_GRAD and the same cfg.
  * The active set is the one of the forward solution (controls equal to a
  * bound are held fixed).
+ * grad_dyn [B][8] (may be NULL) receives, per instance, dL/d of the model
+ * constants in the field order of dmpc_quad_params (mass, Jxx, Jyy, Jzz, arm,
+ * kappa, dt, g): the gradients with respect to the linearised dynamics F_t
+ * and its offset f_t (after Amos et al.) carried to the constants through
+ * F_t = df/dz and f_t = f - F_t z* at the solution.  A caller with one set of
+ * constants for the whole batch sums over instances.
  * dyn, Q, p, u_lo, u_hi: the forward's inputs, unchanged since that call.
  * They are read only when cfg->ckpt_every > 0 (the stage factors are then
- * recomputed from the checkpoints) and may be NULL otherwise; a NULL one with
- * checkpointing is DMPC_EINVAL. */
+ * recomputed from the checkpoints) or, dyn, Q and p, when grad_dyn is not
+ * NULL, and may be NULL otherwise; a NULL one that is needed is DMPC_EINVAL. */
 int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* Q, const float* p,
                   const float* u_lo, const float* u_hi, const void* workspace, size_t workspace_bytes,
                   const float* grad_u, const float* grad_x, float* grad_Q, float* grad_p, float* grad_x0,
-                  void* stream);
+                  float* grad_dyn, void* stream);
 
 /* Number of kernel launches the last dmpc_forward / dmpc_backward issued on
  * this handle (host-side count; for tests of the launch structure). */

@@ -68,7 +68,7 @@ def lib():
         L.dmpc_workspace_bytes.argtypes = [C.POINTER(Config)]
         L.dmpc_workspace_bytes.restype = sz
         L.dmpc_forward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 10 + [vp, sz, vp, vp]
-        L.dmpc_backward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 5 + [sz] + [vp] * 5 + [vp]
+        L.dmpc_backward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 5 + [sz] + [vp] * 6 + [vp]
         L.dmpc_last_launch_count.argtypes = [vp]
         L.dmpc_autotune.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 10 + [vp, sz, vp, C.POINTER(LaunchChoice)]
         L.dmpc_mpc_step.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 6
@@ -203,12 +203,16 @@ def mpc_step(h, cfg, params, T, x_state, u_star, u_warm=None, u_applied=None, st
     h.check(rc, "dmpc_mpc_step")
 
 
-def backward_raw(h, cfg, params, Q, p, u_lo, u_hi, ws, grad_u, grad_x, grad_Q, grad_p, grad_x0, stream=None):
-    """params, Q, p, u_lo, u_hi: the forward's inputs (read only with
-    checkpointing, may be None otherwise)."""
+def backward_raw(h, cfg, params, Q, p, u_lo, u_hi, ws, grad_u, grad_x, grad_Q, grad_p, grad_x0, stream=None,
+                 grad_dyn=None):
+    """params, Q, p, u_lo, u_hi: the forward's inputs (read with
+    checkpointing, and params, Q, p with grad_dyn; may be None otherwise).
+    grad_dyn: [B, 8] output, dL/d(mass, Jxx, Jyy, Jzz, arm, kappa, dt, g)
+    per instance, or None."""
     rc = lib().dmpc_backward(h._h, C.byref(cfg), params if params is not None else QuadParams(),
                              _ptr(Q), _ptr(p), _ptr(u_lo), _ptr(u_hi), _ptr(ws, "uint8"), ws.numel(),
-                             _ptr(grad_u), _ptr(grad_x), _ptr(grad_Q), _ptr(grad_p), _ptr(grad_x0), _stream(stream))
+                             _ptr(grad_u), _ptr(grad_x), _ptr(grad_Q), _ptr(grad_p), _ptr(grad_x0), _ptr(grad_dyn),
+                             _stream(stream))
     h.check(rc, "dmpc_backward")
 
 

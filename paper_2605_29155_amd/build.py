@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdmpc.so")
 SRC = os.path.join(HERE, "csrc", "dmpc.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "dmpc_device.hpp"), os.path.join(ROOT, "include", "dmpc.h")]
+DEPS = [SRC, os.path.join(HERE, "csrc", "dmpc_device.hpp"), os.path.join(HERE, "csrc", "dmpc_theta.hpp"),
+        os.path.join(ROOT, "include", "dmpc.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

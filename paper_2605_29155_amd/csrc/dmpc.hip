@@ -23,6 +23,7 @@
 
 #include "dmpc.h"
 #include "dmpc_device.hpp"
+#include "dmpc_theta.hpp"
 
 using namespace dmpc_dev;
 
@@ -56,6 +57,8 @@ struct KArgs {
   Ws ws;
   const float *gu, *gx;
   float *gQ, *gp, *gx0;
+  float* gdyn;           // [B][8] dL/d(model constants) or null
+  dmpc_quad_params raw;  // model constants as given (for gdyn)
 };
 
 struct Grp {
@@ -878,7 +881,7 @@ __constant__ uint8_t c_pk_j[NPK];
 // the backward vector sweep and first segment first for the forward sweep.
 // The checkpoint is the exact FP64 state of the forward's sweep, so the
 // recomputed factors are the ones the forward would have stored.
-template <bool DENSE, bool CKPT>
+template <bool DENSE, bool CKPT, bool THETA>
 __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
   __shared__ float zz[4][2][20];
   __shared__ double lds[CKPT ? 4 * L_REG : 2];
@@ -985,6 +988,8 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
     float4 K[NX];
     float zs[NZ];
     float fr[NZ];
+    float crow[DENSE ? NZ : 1];  // row l of C_t (THETA)
+    float cl, gl;                // c_t and dL/dx*_t at row l (THETA)
   };
   auto fload = [&](int t, int a0, FStage& S) {
     const float* tp = tail_at(A, b, CKPT ? t - a0 : t);
@@ -996,10 +1001,35 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
     // row l of F = [A | B]: column c stored at c * 16
 #pragma unroll
     for (int c = 0; c < NZ; ++c) S.fr[c] = tp[c * 16 + (l < NX ? l : 0)];
+    if constexpr (THETA) {
+      const int r = l < NX ? l : 0;
+      if constexpr (DENSE) {
+        const float* q = A.Q + srow * NPK;
+#pragma unroll
+        for (int c = 0; c < NZ; ++c) {
+          const int i = r < c ? r : c, j = r < c ? c : r;  // packed upper triangle, row-major
+          S.crow[c] = q[i * NZ - i * (i - 1) / 2 + (j - i)];
+        }
+      } else {
+        S.crow[0] = A.Q[srow * NZ + r];
+      }
+      S.cl = A.p[srow * NZ + r];
+      S.gl = A.gx ? A.gx[srow * NX + r] : 0.f;
+    }
   };
   float xt[NX];
 #pragma unroll
   for (int i = 0; i < NX; ++i) xt[i] = 0.f;
+  // gradient w.r.t. the model constants: lane j < 8 carries the sensitivities
+  // xi_j, eta_j of constant j (forward form of the two costate sums)
+  float sxi[THETA ? NX : 1], seta[THETA ? NX : 1];
+  double gth = 0.0;
+  dmpc_theta::PN PN;
+  if constexpr (THETA) {
+#pragma unroll
+    for (int i = 0; i < NX; ++i) sxi[i] = seta[i] = 0.f;
+    PN = dmpc_theta::make_pn(A.raw, l < 8 ? l : 0);
+  }
   FStage cf, nf;
   for (int sg = 0; sg < nseg; ++sg) {
     const int a = sg * seg, e = (a + seg < T) ? a + seg : T;
@@ -1037,6 +1067,39 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
         }
       }
       lds_sync();
+      if constexpr (THETA) {
+        // row l of (C z~ + dL/dz*)_x and of (C z* + c)_x, then
+        // gth += ht^T xi_j + hs^T eta_j and one RK4 step of the sensitivities
+        float ht, hs;
+        if constexpr (DENSE) {
+          ht = cf.gl;
+          hs = cf.cl;
+#pragma unroll
+          for (int c = 0; c < NX; ++c) {
+            ht = fmaf(cf.crow[c], xt[c], ht);
+            hs = fmaf(cf.crow[c], cf.zs[c], hs);
+          }
+#pragma unroll
+          for (int a4 = 0; a4 < NU; ++a4) {
+            ht = fmaf(cf.crow[NX + a4], ut[a4], ht);
+            hs = fmaf(cf.crow[NX + a4], cf.zs[NX + a4], hs);
+          }
+        } else {
+          float xl = xt[0], zl = cf.zs[0];
+#pragma unroll
+          for (int c = 1; c < NX; ++c) {
+            xl = (l == c) ? xt[c] : xl;
+            zl = (l == c) ? cf.zs[c] : zl;
+          }
+          ht = fmaf(cf.crow[0], xl, cf.gl);
+          hs = fmaf(cf.crow[0], zl, cf.cl);
+        }
+        float dot = 0.f;
+#pragma unroll
+        for (int k = 0; k < NX; ++k) dot = fmaf(rb(ht, k), sxi[k], fmaf(rb(hs, k), seta[k], dot));
+        gth += (double)dot;
+        if (t + 1 < T && l < 8) dmpc_theta::propagate(PN, cf.zs, cf.zs + NX, xt, ut, sxi, seta);
+      }
       if (t + 1 < T) {
         float xi = 0.f;
         if (l < NX) {
@@ -1055,6 +1118,9 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
     const size_t srow = (size_t)b * Tm + t;
     for (int ee = l; ee < NZ; ee += 16) A.gp[srow * NZ + ee] = 0.f;
     for (int m = l; m < W; m += 16) A.gQ[srow * W + m] = 0.f;
+  }
+  if constexpr (THETA) {
+    if (l < 8) A.gdyn[(size_t)b * 8 + l] = (float)gth;
   }
 }
 
@@ -1515,7 +1581,7 @@ int dmpc_last_launch_choice(dmpc_handle h, dmpc_launch_choice* choice) {
 int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* Q, const float* p,
                   const float* u_lo, const float* u_hi, const void* workspace, size_t workspace_bytes,
                   const float* grad_u, const float* grad_x, float* grad_Q, float* grad_p, float* grad_x0,
-                  void* stream) {
+                  float* grad_dyn, void* stream) {
   if (!h) return fail(nullptr, DMPC_EINVAL, "NULL handle");
   int rc = check_cfg(cfg);
   if (rc) return fail(h, rc, "invalid configuration");
@@ -1526,7 +1592,10 @@ int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, c
   const bool ckpt = cfg->ckpt_every > 0;
   if (ckpt && (!Q || !p || !u_lo || !u_hi))
     return fail(h, DMPC_EINVAL, "checkpointed backward needs the forward's Q, p, u_lo, u_hi");
-  if (ckpt && (!(dyn.mass > 0.f) || !(dyn.Jxx > 0.f) || !(dyn.Jyy > 0.f) || !(dyn.Jzz > 0.f) || !(dyn.dt > 0.f)))
+  const bool theta = grad_dyn != nullptr;
+  if (theta && (!Q || !p)) return fail(h, DMPC_EINVAL, "grad_dyn needs the forward's Q and p");
+  if ((ckpt || theta) &&
+      (!(dyn.mass > 0.f) || !(dyn.Jxx > 0.f) || !(dyn.Jyy > 0.f) || !(dyn.Jzz > 0.f) || !(dyn.dt > 0.f)))
     return fail(h, DMPC_EINVAL, "non-positive mass, inertia or step");
   const Layout L = make_layout(cfg);
   if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace & 255))
@@ -1539,19 +1608,34 @@ int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, c
   A.gQ = grad_Q;
   A.gp = grad_p;
   A.gx0 = grad_x0;
+  A.gdyn = grad_dyn;
+  A.raw = dyn;
   hipStream_t s = (hipStream_t)stream;
   const bool dense = cfg->cost_kind == DMPC_COST_DENSE;
-  if (ckpt) {
+  if (ckpt || theta) {
     A.P = make_dyn(dyn);
     A.Q = Q;
     A.p = p;
     A.lo = u_lo;
     A.hi = u_hi;
-    if (dense) k_bwd<true, true><<<A.nquads, 64, 0, s>>>(A);
-    else k_bwd<false, true><<<A.nquads, 64, 0, s>>>(A);
+  }
+  const int g = A.nquads;
+  if (ckpt) {
+    if (theta) {
+      if (dense) k_bwd<true, true, true><<<g, 64, 0, s>>>(A);
+      else k_bwd<false, true, true><<<g, 64, 0, s>>>(A);
+    } else {
+      if (dense) k_bwd<true, true, false><<<g, 64, 0, s>>>(A);
+      else k_bwd<false, true, false><<<g, 64, 0, s>>>(A);
+    }
   } else {
-    if (dense) k_bwd<true, false><<<A.nquads, 64, 0, s>>>(A);
-    else k_bwd<false, false><<<A.nquads, 64, 0, s>>>(A);
+    if (theta) {
+      if (dense) k_bwd<true, false, true><<<g, 64, 0, s>>>(A);
+      else k_bwd<false, false, true><<<g, 64, 0, s>>>(A);
+    } else {
+      if (dense) k_bwd<true, false, false><<<g, 64, 0, s>>>(A);
+      else k_bwd<false, false, false><<<g, 64, 0, s>>>(A);
+    }
   }
   h->last_launches = 1;
   return hip_check(h, hipGetLastError(), "kernel launch");

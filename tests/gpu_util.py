@@ -26,7 +26,7 @@ def rel(a, b, axis_from=1):
 
 
 def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=True, grad_u=None, grad_x=None,
-            fp64_pivot=1e-6, ckpt=0):
+            fp64_pivot=1e-6, ckpt=0, theta=False):
     import torch
 
     import paper_2605_29155_amd as D
@@ -53,7 +53,8 @@ def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=Tru
         gQ = torch.full_like(t["Q"], float("nan"))
         gp = torch.full_like(t["p"], float("nan"))
         gx0 = torch.full_like(t["x0"], float("nan"))
-        D.backward_raw(h, cfg, par, t["Q"], t["p"], t["lo"], t["hi"], ws, gu, gx, gQ, gp, gx0)
+        gd = torch.full((B, 8), float("nan"), device=dev) if theta else None
+        D.backward_raw(h, cfg, par, t["Q"], t["p"], t["lo"], t["hi"], ws, gu, gx, gQ, gp, gx0, grad_dyn=gd)
         out["launches_bwd"] = h.launch_count()
     torch.cuda.synchronize()
     out.update(u=u.cpu().numpy(), x=x.cpu().numpy(), status=st.cpu().numpy().astype(np.uint32), K=K)
@@ -61,6 +62,8 @@ def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=Tru
         out["dlog"] = dl.cpu().numpy()
     if need_grad:
         out.update(dQ=gQ.cpu().numpy(), dp=gp.cpu().numpy(), dx0=gx0.cpu().numpy())
+        if theta:
+            out["gdyn"] = gd.cpu().numpy()
     return out
 
 
@@ -81,7 +84,8 @@ def oracle_replay(d, g, idx=None, grad_u=None, grad_x=None):
     out = dict(replay=fr, free=ff, iters=iters, alpha=alpha, pattern=pattern)
     if "dQ" in g:
         mask = orc.active_mask(g["u"][sel], lo, hi, T)
-        out["bwd"] = orc.backward(P, x0, Q, p, lo, hi, fr["u"], fr["x"], gu, gx, T=T, mask=mask)
+        out["bwd"] = orc.backward(P, x0, Q, p, lo, hi, fr["u"], fr["x"], gu, gx, T=T, mask=mask,
+                                  dtheta="gdyn" in g)
     return out
 
 

@@ -68,7 +68,7 @@ def test_calls_without_handle_fail_cleanly(D):
     assert rc == -1
     assert L.dmpc_mpc_step(None, C.byref(cfg), p, None, None, None, None, None, None) == -1
     rc = L.dmpc_backward(None, C.byref(cfg), D.QuadParams(), None, None, None, None, None, 0, None, None, None, None,
-                         None, None)
+                         None, None, None)
     assert rc == -1
     assert L.dmpc_last_launch_count(None) == -1
     assert b"handle" in L.dmpc_last_error(None)

@@ -126,14 +126,21 @@ def test_error_codes():
                         None, ptr(st), ptr(ws), n, None, s)
     assert rc == -1
     rc = L.dmpc_backward(h._h, C.byref(cfg), par, None, None, None, None, ptr(ws), n, ptr(u), None, ptr(Q), ptr(p),
-                         ptr(x0), s)
+                         ptr(x0), None, s)
     assert rc == -1  # forward was not run with NEED_GRAD
     # a checkpointed backward needs the forward's cost and bounds
     cc = D.make_config(8, 10, 0, 5, 0.0, D.NEED_GRAD, ckpt_every=4)
     wc = D.alloc_workspace(cc, dev)
     gu = torch.zeros(8, 10, 4, device=dev)
     rc = L.dmpc_backward(h._h, C.byref(cc), par, None, ptr(p), ptr(lo), ptr(hi), ptr(wc), wc.numel(), ptr(gu), None,
-                         ptr(Q), ptr(p), ptr(x0), s)
+                         ptr(Q), ptr(p), ptr(x0), None, s)
+    assert rc == -1
+    # the gradient w.r.t. the model constants needs the forward's cost
+    gd = torch.zeros(8, 8, device=dev)
+    cg = D.make_config(8, 10, 0, 5, 0.0, D.NEED_GRAD)
+    wg = D.alloc_workspace(cg, dev)
+    rc = L.dmpc_backward(h._h, C.byref(cg), par, None, None, None, None, ptr(wg), wg.numel(), ptr(gu), None,
+                         ptr(Q), ptr(p), ptr(x0), ptr(gd), s)
     assert rc == -1
     assert D.validate(D.make_config(8, 10, 0, 5, 0.0, 0, ckpt_every=-1)) == -1
     # B = 0: nothing to do, no launches
