@@ -41,7 +41,8 @@ def flops_per_solve(T, K, dense=False):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("paper_2605_29155_amd/csrc/dmpc.hip", "paper_2605_29155_amd/csrc/dmpc_device.hpp", "include/dmpc.h"):
+    for f in ("paper_2605_29155_amd/csrc/dmpc.hip", "paper_2605_29155_amd/csrc/dmpc_device.hpp",
+              "paper_2605_29155_amd/csrc/dmpc_theta.hpp", "include/dmpc.h"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -73,6 +73,13 @@ extern "C" {
 #define DMPC_TUNED 0x8u     /* use the launch choice dmpc_autotune (or dmpc_set_tuned) stored on the
                                handle for this problem shape, instead of DMPC_PLAIN / DMPC_LPT; without
                                a stored choice the flags decide */
+#define DMPC_TPAR 0x10u     /* per-launch form whose backward pass is a time-parallel Riccati: an
+                               associative scan over the stages (ceil(log2 T_max) launches per
+                               iteration) under the previous iteration's clamp pattern, checked stage
+                               by stage; instances whose check fails take the serial sweep.  Same
+                               results as the serial form up to rounding; meant for small B and long
+                               T, where the serial recursion in time sets the latency.  Sizes the
+                               workspace for it (16 KiB more per instance-stage) */
 
 /* per-instance status word */
 #define DMPC_ST_CONVERGED 0x1u   /* tol_du > 0 and ||U^k - U^{k-1}||_inf < tol_du was reached */
@@ -113,7 +120,7 @@ typedef struct {
                          recomputes the factors segment by segment (twice) from those checkpoints;
                          the gradients are the same.  Checkpointing for long horizons. */
   float fp64_pivot;   /* pivot threshold below which a stage sets DMPC_ST_FP64; <= 0 disables */
-  uint32_t flags;     /* DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT | DMPC_TUNED */
+  uint32_t flags;     /* DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT | DMPC_TUNED | DMPC_TPAR */
 } dmpc_config;
 
 /* How a forward is launched.  None of these changes the arithmetic of the
@@ -121,7 +128,8 @@ typedef struct {
  * per-launch form agrees with it to rounding (it forms A_t, B_t in a separate
  * launch). */
 typedef struct {
-  int32_t plain;          /* 1: per-launch form (3 launches per iteration); 0: one persistent launch */
+  int32_t plain;          /* 1: per-launch form (3 launches per iteration); 2: per-launch form with the
+                             time-parallel Riccati (DMPC_TPAR workspace); 0: one persistent launch */
   int32_t lpt;            /* persistent: take instances by decreasing T_b (needs the T array) */
   int32_t waves_per_simd; /* persistent: 1 = registers uncapped; 2 = capped at 256 so that two waves
                              share a SIMD (helps when there are more instances than 4 per SIMD) */

@@ -17,7 +17,7 @@ from . import build as _build
 
 NX, NU, NZ, NPACK = 13, 4, 17, 153
 COST_DIAG, COST_DENSE = 0, 1
-NEED_GRAD, PLAIN, LPT, TUNED = 0x1, 0x2, 0x4, 0x8
+NEED_GRAD, PLAIN, LPT, TUNED, TPAR = 0x1, 0x2, 0x4, 0x8, 0x10
 ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_FP64, ST_QPMAXITER, ST_REGULARIZED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 ITERS_SHIFT = 8
 ALPHA_NONE = 255
@@ -297,18 +297,21 @@ class DMPCLayer:
     """Callable layer: (x0, Q, p, u_lo, u_hi, T=None) -> (u*, x*, status)."""
 
     def __init__(self, params, max_iter=5, tol_du=0.0, cost_kind=COST_DIAG, plain=False, lpt=True,
-                 fp64_pivot=1e-6, ckpt_every=0, autotune=False, device=0):
+                 fp64_pivot=1e-6, ckpt_every=0, autotune=False, tpar=False, device=0):
         """autotune: on the first call for a shape, time the launch choices
-        (dmpc_autotune) and use the fastest for that shape from then on."""
+        (dmpc_autotune) and use the fastest for that shape from then on.
+        tpar: per-launch form with the time-parallel Riccati (small B, long T)."""
         self.handle = Handle(device)
         self.autotune = autotune
         self.params = quad_params(params) if isinstance(params, dict) else params
         self.max_iter, self.tol_du, self.cost_kind = max_iter, tol_du, cost_kind
         self.plain, self.lpt, self.fp64_pivot, self.ckpt_every = plain, lpt, fp64_pivot, ckpt_every
+        self.tpar = tpar
 
     def config(self, B, T_max, need_grad=True):
         flags = (NEED_GRAD if need_grad else 0) | (PLAIN if self.plain else 0) | (LPT if self.lpt else 0)
         flags |= TUNED if self.autotune else 0
+        flags |= TPAR if self.tpar else 0
         return make_config(B, T_max, self.cost_kind, self.max_iter, self.tol_du, flags, self.fp64_pivot,
                            self.ckpt_every)
 

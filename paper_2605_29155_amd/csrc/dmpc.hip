@@ -40,6 +40,8 @@ struct Ws {
                 //   or (checkpointing) one segment, recomputed by the backward
   float* ktil;  // [B][Tm][4]   (backward scratch)
   double* ck;   // [B][nck][CK_W] checkpoints of (V, v) at stages j * ckpt
+  double* elem;  // [2][B][Tm][EL_W] time-parallel Riccati elements (ping-pong), or null
+  uint8_t* pat;  // [B][Tm] clamp pattern of the last backward pass (time-parallel guess), or null
 };
 
 struct KArgs {
@@ -47,6 +49,7 @@ struct KArgs {
   int B, Tm, K, need_grad, use_order, nquads;
   int ckpt, nck, tstride;  // checkpoint interval (0 = off), checkpoints per instance, tail stages per instance
   int has_lin;             // the workspace holds the per-launch form's linearisation buffer
+  int tpar;                // per-launch form with the time-parallel Riccati: serial sweep only as fallback
   float tol, piv;
   const float *x0, *Q, *p, *lo, *hi;
   const float* uinit;  // [B][Tm][4] initial controls (warm start) or null (hover thrust)
@@ -497,14 +500,15 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
         for (int a = 0; a < 4; ++a) gp[a * 16 + l] = Kc[a];
       }
       if (l == NX) *(float4*)(gp + 64) = make_float4((float)kv[0], (float)kv[1], (float)kv[2], (float)kv[3]);
-      if (A.dlog && l == 0) {
+      if ((A.dlog || A.ws.pat) && l == 0) {
         unsigned code = 0;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
           const unsigned c = (fr[a] != 0.0) ? 0u : (kv[a] <= dl[a] ? 1u : 2u);
           code |= c << (2 * a);
         }
-        A.dlog[((size_t)b * A.K + kit) * (1 + A.Tm) + 1 + t] = (uint8_t)code;
+        if (A.dlog) A.dlog[((size_t)b * A.K + kit) * (1 + A.Tm) + 1 + t] = (uint8_t)code;
+        if (A.ws.pat) A.ws.pat[(size_t)b * A.Tm + t] = (uint8_t)code;
       }
     } else if (MODE == 1) {
       float* tp = tail_at(A, b, t - tbase);
@@ -781,6 +785,10 @@ __global__ __launch_bounds__(64) void k_plain_init(KArgs A) {
   if (!G.valid) return;
   if (G.T > 0) grp_init(A, G);
   grp_write_state(A, G, 0, 0, 0u, G.T > 0 ? 0 : 1);
+  if (A.tpar) {
+    if (l == 0) A.ws.state[(size_t)G.b * SW + S_FB] = 0;
+    for (int t = l; t < A.Tm; t += 16) A.ws.pat[(size_t)G.b * A.Tm + t] = 0;
+  }
 }
 
 // linearisation of every stage along the nominal: one 16-lane row per (b, t)
@@ -812,10 +820,13 @@ __global__ __launch_bounds__(64) void k_plain_riccati(KArgs A) {
   if (!G.valid || G.T == 0) return;
   int* s = A.ws.state + (size_t)G.b * SW;
   if (MODE == 0 && s[S_DONE]) return;
+  // with the time-parallel Riccati this sweep runs only where its pattern check failed
+  if (MODE == 0 && A.tpar && !s[S_FB]) return;
   uint32_t st = 0;
   grp_sweep<DENSE, MODE, false>(A, G, s[S_NOM], s[S_ITERS], L, st, G.T);
   mem_fence_wg();
   if (l == 0 && st) atomicOr((unsigned*)&s[S_STATUS], st);
+  if (MODE == 0 && A.tpar && l == 0) s[S_FB] = 0;
 }
 
 template <bool DENSE>
@@ -864,6 +875,433 @@ __global__ __launch_bounds__(64) void k_plain_finalize(KArgs A) {
     s[S_STATUS] = (int)st;
     s[S_DONE] = 1;
     A.status[G.b] = st | ((uint32_t)iters << DMPC_ST_ITERS_SHIFT);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// time-parallel Riccati (per-launch form with DMPC_TPAR)
+//
+// The backward pass of one iteration solves, for a given clamp pattern, the
+// LQ problem in deviations from the nominal: dx' = A dx + B du, stage cost
+// 1/2 dz^T C dz + g^T dz (g = C z_bar + c), clamped controls held at their
+// bound.  Its value functions V_t(dx) = 1/2 dx^T V_t dx + v_t^T dx are suffix
+// products of one element per stage under an associative combination (the
+// conditional value functions of Saerkkae and Garcia-Fernandez's temporal
+// parallelisation of dynamic programming, the associative-scan route the
+// paper cites as the alternative to the serial recursion in time):
+//   element t:  (A, b, C, eta, J) with V_{t->t+1}(x, y) = 1/2 x^T J x - eta^T x
+//               + 1/2 w^T C^+ w for y = A x + b + w, w in range(C)
+//   (i then j): A = A_j M^-1 A_i,  b = A_j M^-1 (b_i + C_i eta_j) + b_j,
+//               C = A_j M^-1 C_i A_j^T + C_j,
+//               eta = A_i^T M^-T (eta_j - J_j b_i) + eta_i,
+//               J = A_i^T M^-T J_j A_i + J_i,      M = I + C_i J_j,
+// and the last stage's element is terminal (A = 0, b = 0, C = 0), so the
+// suffix product from t holds V_t = J and v_t = -eta.  The element of stage
+// t < T-1 removes the cross term and the clamped controls from the stage:
+// with R = C_ff (free controls f, clamped c held at k_c),
+//   r = C_fc k_c + g_f,  J = C_xx - C_xf R^-1 C_fx,
+//   eta = -(g_x + C_xc k_c - C_xf R^-1 r),  A = A_t - B_f R^-1 C_fx,
+//   b = B_c k_c - B_f R^-1 r,  C = B_f R^-1 B_f^T.
+// The clamp pattern is not known before V_{t+1} is: each iteration takes the
+// previous iteration's pattern (free at the first), and the gains kernel
+// re-solves every stage's box-QP with the scanned V_{t+1}.  If every stage
+// reproduces the assumed pattern, then by induction from the last stage the
+// serial recursion would have taken the same decisions and computed the same
+// V (up to rounding); otherwise the instance is flagged and its serial sweep
+// runs instead.  One wavefront per (instance, stage); FP64 throughout.
+// ---------------------------------------------------------------------------
+
+constexpr int EL_A = 0, EL_B = 169, EL_C = 182, EL_E = 351, EL_J = 364, EL_W = 536;  // doubles per element
+
+__device__ __forceinline__ double* elem_at(const KArgs& A, int buf, int b, int t) {
+  return A.ws.elem + (((size_t)buf * A.B + b) * A.Tm + t) * EL_W;
+}
+
+// out = op(X) op(Y) for 13 x 13 row-major matrices in LDS (tX / tY transpose)
+__device__ __forceinline__ void lds_mm(double* out, const double* X, const double* Y, bool tX, bool tY) {
+  for (int idx = threadIdx.x; idx < 169; idx += 64) {
+    const int r = idx / 13, c = idx % 13;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 13; ++k) s = fma(tX ? X[k * 13 + r] : X[r * 13 + k], tY ? Y[c * 13 + k] : Y[k * 13 + c], s);
+    out[idx] = s;
+  }
+  __syncthreads();
+}
+
+// out = op(X) y for a 13 x 13 matrix and a 13-vector
+__device__ __forceinline__ void lds_mv(double* out, const double* X, const double* y, bool tX) {
+  if (threadIdx.x < 13) {
+    const int r = threadIdx.x;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 13; ++k) s = fma(tX ? X[k * 13 + r] : X[r * 13 + k], y[k], s);
+    out[r] = s;
+  }
+  __syncthreads();
+}
+
+// masked inverse of the free block of a symmetric positive definite 4 x 4
+// matrix (zero rows and columns on clamped controls), by Gauss-Jordan on the
+// free block with the clamped rows replaced by identity (no pivoting is needed
+// for a positive definite block); every thread computes it
+__device__ __forceinline__ void masked_inv4(const double* H, const bool* fr, double* M) {
+  double a[4][8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[i][j] = (j < 4) ? ((fr[i] && fr[j]) ? H[i * 4 + j] : (i == j ? 1.0 : 0.0))
+                                                  : ((j - 4) == i ? 1.0 : 0.0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double ip = 1.0 / a[k][k];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[k][j] *= ip;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (r == k) continue;
+      const double f = a[r][k];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a[r][j] = fma(-f, a[k][j], a[r][j]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) M[i * 4 + j] = (fr[i] && fr[j]) ? a[i][4 + j] : 0.0;
+}
+
+// stage cost matrix C_t (17 x 17, LDS) and g_t = C_t z_bar + c_t
+template <bool DENSE>
+__device__ __forceinline__ void stage_cost_lds(const KArgs& A, size_t srow, const float* zb, double* C, double* g) {
+  for (int idx = threadIdx.x; idx < NZ * NZ; idx += 64) {
+    const int i = idx / NZ, j = idx % NZ;
+    double v;
+    if (DENSE) v = (double)A.Q[srow * NPK + (i <= j ? pidx(i, j) : pidx(j, i))];
+    else v = (i == j) ? (double)A.Q[srow * NZ + i] : 0.0;
+    C[idx] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NZ) {
+    const int i = threadIdx.x;
+    double s = (double)A.p[srow * NZ + i];
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) s = fma(C[i * NZ + j], (double)zb[j], s);
+    g[i] = s;
+  }
+  __syncthreads();
+}
+
+// F = [A | B] of stage t (13 x 17, LDS, row-major) from the linearisation
+// buffer; column 0 (position x) is e_0 exactly and is not stored there
+__device__ __forceinline__ void load_F(const KArgs& A, int b, int t, double* F) {
+  const float* fp = lin_at(A, b, t);
+  for (int idx = threadIdx.x; idx < NX * NZ; idx += 64) {
+    const int r = idx / NZ, c = idx % NZ;
+    F[idx] = (c == 0) ? (r == 0 ? 1.0 : 0.0) : (double)fp[c * 16 + r];
+  }
+  __syncthreads();
+}
+
+template <bool DENSE>
+__global__ __launch_bounds__(64) void k_tpar_elem(KArgs A) {
+  __shared__ double C[NZ * NZ], F[NX * NZ], g[NZ], T1[NX * 4], W[NX * 4];
+  const int unit = blockIdx.x, b = unit / A.Tm, t = unit % A.Tm;
+  const int* s = A.ws.state + (size_t)b * SW;
+  const int T = s[S_T];
+  if (t >= T || s[S_DONE]) return;
+  const size_t srow = (size_t)b * A.Tm + t;
+  const int n = s[S_NOM];
+  float zb[NZ];
+  load_z(traj_at(A, b, n, t), zb);
+  const bool term = (t + 1 == T);
+  stage_cost_lds<DENSE>(A, srow, zb, C, g);
+  if (!term) load_F(A, b, t, F);
+  // assumed pattern: free, or clamped at the lower / upper bound
+  const unsigned code = A.ws.pat[srow];
+  bool fr[4];
+  double kc[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const unsigned c = (code >> (2 * a)) & 3u;
+    fr[a] = (c == 0);
+    const double lo = (double)A.lo[(size_t)b * 4 + a] - (double)zb[NX + a];
+    const double hi = (double)A.hi[(size_t)b * 4 + a] - (double)zb[NX + a];
+    kc[a] = (c == 0) ? 0.0 : (c == 1 ? lo : hi);
+  }
+  double Ruu[16], iR[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Ruu[i * 4 + j] = C[(NX + i) * NZ + NX + j];
+  masked_inv4(Ruu, fr, iR);
+  // r = C_fc k_c + g_f on the free controls (0 on clamped ones)
+  double r[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double v = g[NX + a];
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) v = fma(fr[bb] ? 0.0 : Ruu[a * 4 + bb], kc[bb], v);
+    r[a] = fr[a] ? v : 0.0;
+  }
+  // T1 = C_xu R^-1 (13 x 4) and W = B R^-1 (13 x 4), free columns only
+  if (threadIdx.x < NX) {
+    const int i = threadIdx.x;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        s1 = fma(C[i * NZ + NX + bb], iR[bb * 4 + a], s1);
+        if (!term) s2 = fma(F[i * NZ + NX + bb], iR[bb * 4 + a], s2);
+      }
+      T1[i * 4 + a] = s1;
+      W[i * 4 + a] = s2;
+    }
+  }
+  __syncthreads();
+  double* E = elem_at(A, 0, b, t);
+  for (int idx = threadIdx.x; idx < 169; idx += 64) {
+    const int i = idx / 13, j = idx % 13;
+    // J = C_xx - C_xu R^-1 C_ux, symmetrised
+    double Jv = C[i * NZ + j], Jw = C[j * NZ + i], Av = 0.0, Cv = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      Jv = fma(-T1[i * 4 + a], C[(NX + a) * NZ + j], Jv);
+      Jw = fma(-T1[j * 4 + a], C[(NX + a) * NZ + i], Jw);
+    }
+    Jv = 0.5 * (Jv + Jw);
+    if (!term) {
+      Av = F[i * NZ + j];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        Av = fma(-W[i * 4 + a], C[(NX + a) * NZ + j], Av);
+        Cv = fma(W[i * 4 + a], F[j * NZ + NX + a], Cv);
+      }
+    }
+    E[EL_J + idx] = Jv;
+    E[EL_A + idx] = Av;
+    E[EL_C + idx] = Cv;
+  }
+  if (threadIdx.x < NX) {
+    const int i = threadIdx.x;
+    // eta = -(g_x + C_xc k_c - C_xu R^-1 r),  b = B_c k_c - B R^-1 r
+    double q = g[i], bv = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      q = fma(fr[a] ? 0.0 : C[i * NZ + NX + a], kc[a], q);
+      q = fma(-T1[i * 4 + a], r[a], q);
+      if (!term) {
+        bv = fma(fr[a] ? 0.0 : F[i * NZ + NX + a], kc[a], bv);
+        bv = fma(-W[i * 4 + a], r[a], bv);
+      }
+    }
+    E[EL_E + i] = -q;
+    E[EL_B + i] = bv;
+  }
+}
+
+// one level of the suffix scan: out[t] = in[t] (x) in[t + step] (or in[t])
+__global__ __launch_bounds__(64) void k_tpar_scan(KArgs A, int step, int src) {
+  __shared__ double Ai[169], Ci[169], Ji[169], Aj[169], Cj[169], Jj[169], bi[13], ei[13], bj[13], ej[13];
+  __shared__ double Aug[13 * 26], X1[169], X2[169], v1[13], v2[13], fac[13];
+  const int unit = blockIdx.x, b = unit / A.Tm, t = unit % A.Tm;
+  const int* s = A.ws.state + (size_t)b * SW;
+  const int T = s[S_T];
+  if (t >= T || s[S_DONE]) return;
+  const double* ein = elem_at(A, src, b, t);
+  double* eout = elem_at(A, 1 - src, b, t);
+  if (t + step >= T) {
+    for (int k = threadIdx.x; k < EL_W; k += 64) eout[k] = ein[k];
+    return;
+  }
+  const double* ejn = elem_at(A, src, b, t + step);
+  for (int k = threadIdx.x; k < 169; k += 64) {
+    Ai[k] = ein[EL_A + k];
+    Ci[k] = ein[EL_C + k];
+    Ji[k] = ein[EL_J + k];
+    Aj[k] = ejn[EL_A + k];
+    Cj[k] = ejn[EL_C + k];
+    Jj[k] = ejn[EL_J + k];
+  }
+  if (threadIdx.x < 13) {
+    const int k = threadIdx.x;
+    bi[k] = ein[EL_B + k];
+    ei[k] = ein[EL_E + k];
+    bj[k] = ejn[EL_B + k];
+    ej[k] = ejn[EL_E + k];
+  }
+  __syncthreads();
+  // [M | I] with M = I + C_i J_j
+  lds_mm(X1, Ci, Jj, false, false);
+  for (int idx = threadIdx.x; idx < 13 * 26; idx += 64) {
+    const int r = idx / 26, c = idx % 26;
+    Aug[idx] = (c < 13) ? X1[r * 13 + c] + (r == c ? 1.0 : 0.0) : ((c - 13) == r ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  // Gauss-Jordan with partial pivoting: Aug -> [I | M^-1]
+  for (int k = 0; k < 13; ++k) {
+    // pivot: largest |M[r][k]| over r >= k, by a reduction over the first 16 lanes
+    double best = (threadIdx.x >= k && threadIdx.x < 13) ? fabs(Aug[threadIdx.x * 26 + k]) : -1.0;
+    int arg = threadIdx.x;
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 16);
+      const int oa = __shfl_xor(arg, off, 16);
+      if (ob > best || (ob == best && oa < arg)) {
+        best = ob;
+        arg = oa;
+      }
+    }
+    const int p = __shfl(arg, 0, 64);
+    if (p != k && threadIdx.x < 26) {
+      const int c = threadIdx.x;
+      const double tmp = Aug[k * 26 + c];
+      Aug[k * 26 + c] = Aug[p * 26 + c];
+      Aug[p * 26 + c] = tmp;
+    }
+    __syncthreads();
+    const double ip = 1.0 / Aug[k * 26 + k];
+    if (threadIdx.x < 13) fac[threadIdx.x] = Aug[threadIdx.x * 26 + k];
+    __syncthreads();
+    if (threadIdx.x < 26) Aug[k * 26 + threadIdx.x] *= ip;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 13 * 26; idx += 64) {
+      const int r = idx / 26, c = idx % 26;
+      if (r != k) Aug[idx] = fma(-fac[r], Aug[k * 26 + c], Aug[idx]);
+    }
+    __syncthreads();
+  }
+  // X2 = M^-1
+  for (int idx = threadIdx.x; idx < 169; idx += 64) X2[idx] = Aug[(idx / 13) * 26 + 13 + idx % 13];
+  __syncthreads();
+  // b = A_j M^-1 (b_i + C_i eta_j) + b_j
+  lds_mv(v1, Ci, ej, false);
+  if (threadIdx.x < 13) v1[threadIdx.x] += bi[threadIdx.x];
+  __syncthreads();
+  lds_mv(v2, X2, v1, false);
+  lds_mv(v1, Aj, v2, false);
+  if (threadIdx.x < 13) eout[EL_B + threadIdx.x] = v1[threadIdx.x] + bj[threadIdx.x];
+  // eta = A_i^T M^-T (eta_j - J_j b_i) + eta_i
+  lds_mv(v1, Jj, bi, false);
+  if (threadIdx.x < 13) v1[threadIdx.x] = ej[threadIdx.x] - v1[threadIdx.x];
+  __syncthreads();
+  lds_mv(v2, X2, v1, true);
+  lds_mv(v1, Ai, v2, true);
+  if (threadIdx.x < 13) eout[EL_E + threadIdx.x] = v1[threadIdx.x] + ei[threadIdx.x];
+  // A = A_j M^-1 A_i
+  lds_mm(X1, X2, Ai, false, false);  // M^-1 A_i
+  lds_mm(Aug, Aj, X1, false, false); // (Aug reused as a 13 x 13 buffer)
+  for (int k = threadIdx.x; k < 169; k += 64) eout[EL_A + k] = Aug[k];
+  __syncthreads();
+  // C = A_j M^-1 C_i A_j^T + C_j (symmetrised)
+  lds_mm(X1, X2, Ci, false, false);
+  lds_mm(Aug, Aj, X1, false, false);
+  lds_mm(X1, Aug, Aj, false, true);
+  for (int k = threadIdx.x; k < 169; k += 64) {
+    const int r = k / 13, c = k % 13;
+    eout[EL_C + k] = 0.5 * (X1[k] + X1[c * 13 + r]) + Cj[k];
+  }
+  __syncthreads();
+  // J = A_i^T M^-T J_j A_i + J_i (symmetrised)
+  lds_mm(X1, Jj, Ai, false, false);   // J_j A_i
+  lds_mm(Aug, X2, X1, true, false);   // M^-T J_j A_i
+  lds_mm(X1, Ai, Aug, true, false);   // A_i^T M^-T J_j A_i
+  for (int k = threadIdx.x; k < 169; k += 64) {
+    const int r = k / 13, c = k % 13;
+    eout[EL_J + k] = 0.5 * (X1[k] + X1[c * 13 + r]) + Ji[k];
+  }
+}
+
+// gains of every stage from the scanned V_{t+1}: Q = C + F^T V F,
+// q = g + F^T v, the stage's box-QP, K = -Q_ff^-1 Q_fx; the pattern is
+// checked against the one the elements assumed
+template <bool DENSE>
+__global__ __launch_bounds__(64) void k_tpar_gains(KArgs A, int src) {
+  __shared__ double C[NZ * NZ], F[NX * NZ], g[NZ], V[169], v[13], Y[NX * NZ], Q[NZ * NZ], q[NZ];
+  const int unit = blockIdx.x, b = unit / A.Tm, t = unit % A.Tm;
+  int* s = A.ws.state + (size_t)b * SW;
+  const int T = s[S_T];
+  if (t >= T || s[S_DONE]) return;
+  const int kit = s[S_ITERS], n = s[S_NOM];
+  const size_t srow = (size_t)b * A.Tm + t;
+  float zb[NZ];
+  load_z(traj_at(A, b, n, t), zb);
+  stage_cost_lds<DENSE>(A, srow, zb, C, g);
+  const bool has_dyn = (t + 1 < T);
+  if (has_dyn) {
+    load_F(A, b, t, F);
+    const double* E = elem_at(A, src, b, t + 1);
+    for (int k = threadIdx.x; k < 169; k += 64) V[k] = E[EL_J + k];
+    if (threadIdx.x < 13) v[threadIdx.x] = -E[EL_E + threadIdx.x];
+    __syncthreads();
+    // Y = V F (13 x 17)
+    for (int idx = threadIdx.x; idx < NX * NZ; idx += 64) {
+      const int r = idx / NZ, c = idx % NZ;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < NX; ++k) acc = fma(V[r * 13 + k], F[k * NZ + c], acc);
+      Y[idx] = acc;
+    }
+    __syncthreads();
+  }
+  // Q = C + F^T Y, q = g + F^T v
+  for (int idx = threadIdx.x; idx < NZ * NZ; idx += 64) {
+    const int r = idx / NZ, c = idx % NZ;
+    double acc = C[idx];
+    if (has_dyn) {
+#pragma unroll
+      for (int k = 0; k < NX; ++k) acc = fma(F[k * NZ + r], Y[k * NZ + c], acc);
+    }
+    Q[idx] = acc;
+  }
+  if (threadIdx.x < NZ) {
+    const int r = threadIdx.x;
+    double acc = g[r];
+    if (has_dyn) {
+#pragma unroll
+      for (int k = 0; k < NX; ++k) acc = fma(F[k * NZ + r], v[k], acc);
+    }
+    q[r] = acc;
+  }
+  __syncthreads();
+  double H[16], qu[4], dl[4], dh[4], kw[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) H[a * 4 + bb] = 0.5 * (Q[(NX + a) * NZ + NX + bb] + Q[(NX + bb) * NZ + NX + a]);
+    qu[a] = q[NX + a];
+    dl[a] = (double)A.lo[(size_t)b * 4 + a] - (double)zb[NX + a];
+    dh[a] = (double)A.hi[(size_t)b * 4 + a] - (double)zb[NX + a];
+  }
+  float* gp = gains_at(A, b, t);
+  if (kit > 0) {
+    const float4 w = *(const float4*)(gp + 64);
+    kw[0] = w.x; kw[1] = w.y; kw[2] = w.z; kw[3] = w.w;
+  }
+  __syncthreads();  // every thread has read the previous feedforward before it is overwritten
+  double kv[4], fr[4];
+  Chol4 Ch;
+  uint32_t st = 0;
+  boxqp(H, qu, dl, dh, kw, A.piv, kv, fr, Ch, st);
+  unsigned code = 0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) code |= ((fr[a] != 0.0) ? 0u : (kv[a] <= dl[a] ? 1u : 2u)) << (2 * a);
+  if (threadIdx.x < NX) {
+    const int c = threadIdx.x;
+    double Kd[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) Kd[a] = fr[a] * 0.5 * (Q[(NX + a) * NZ + c] + Q[c * NZ + NX + a]);
+    solve4(Ch, Kd);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) gp[a * 16 + c] = (float)(-Kd[a]);
+  }
+  if (threadIdx.x == 0) {
+    *(float4*)(gp + 64) = make_float4((float)kv[0], (float)kv[1], (float)kv[2], (float)kv[3]);
+    if (A.dlog) A.dlog[((size_t)b * A.K + kit) * (1 + A.Tm) + 1 + t] = (uint8_t)code;
+    if (code != A.ws.pat[srow]) atomicOr(&s[S_FB], 1);
+    A.ws.pat[srow] = (uint8_t)code;
+    if (st) atomicOr(&s[S_STATUS], (int)st);
   }
 }
 
@@ -1170,9 +1608,9 @@ __global__ __launch_bounds__(64) void k_mpc_step(Dyn P, int B, int Tm, const int
 // ---------------------------------------------------------------------------
 
 struct Layout {
-  size_t state, queue, order, traj, gains, lin, tail, ktil, ck, total;
+  size_t state, queue, order, traj, gains, lin, tail, ktil, ck, elem, pat, total;
   int tstride, nck;
-  bool has_lin;
+  bool has_lin, has_tpar;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -1184,7 +1622,7 @@ int check_cfg(const dmpc_config* c) {
   if (c->cost_kind != DMPC_COST_DIAG && c->cost_kind != DMPC_COST_DENSE) return DMPC_EUNSUPPORTED;
   if (c->ckpt_every < 0) return DMPC_EINVAL;
   if (!(c->tol_du == c->tol_du) || !(c->fp64_pivot == c->fp64_pivot)) return DMPC_EINVAL;
-  if (c->flags & ~(DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT | DMPC_TUNED)) return DMPC_EINVAL;
+  if (c->flags & ~(DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT | DMPC_TUNED | DMPC_TPAR)) return DMPC_EINVAL;
   return DMPC_OK;
 }
 
@@ -1204,8 +1642,12 @@ Layout make_layout(const dmpc_config* c) {
   L.gains = take(B * Tm * GS * sizeof(float));
   // the per-launch form's linearisation buffer: present when that form may run
   // (requested, or possibly chosen by a tuned launch)
-  L.has_lin = (c->flags & (DMPC_PLAIN | DMPC_TUNED)) != 0;
+  L.has_lin = (c->flags & (DMPC_PLAIN | DMPC_TUNED | DMPC_TPAR)) != 0;
   L.lin = L.has_lin ? take(B * Tm * FS * sizeof(float)) : take(0);
+  // the time-parallel Riccati's two element buffers and pattern guesses
+  L.has_tpar = (c->flags & DMPC_TPAR) != 0;
+  L.elem = take(L.has_tpar ? 2 * B * Tm * EL_W * sizeof(double) : 0);
+  L.pat = take(L.has_tpar ? B * Tm : 0);
   const bool g = (c->flags & DMPC_NEED_GRAD) != 0;
   const int ck = c->ckpt_every;
   // checkpointing keeps one segment of factors per instance (the backward's
@@ -1307,6 +1749,8 @@ KArgs base_args(const dmpc_config* c, void* workspace) {
   A.ws.tail = (float*)(w + L.tail);
   A.ws.ktil = (float*)(w + L.ktil);
   A.ws.ck = (double*)(w + L.ck);
+  A.ws.elem = L.has_tpar ? (double*)(w + L.elem) : nullptr;
+  A.ws.pat = L.has_tpar ? (uint8_t*)(w + L.pat) : nullptr;
   A.ckpt = c->ckpt_every;
   A.nck = L.nck;
   A.tstride = L.tstride;
@@ -1321,7 +1765,7 @@ std::array<int, 6> shape_key(const dmpc_config* c, bool has_T) {
 
 dmpc_launch_choice default_choice(const dmpc_config* c) {
   dmpc_launch_choice d{};
-  d.plain = (c->flags & DMPC_PLAIN) ? 1 : 0;
+  d.plain = (c->flags & DMPC_TPAR) ? 2 : ((c->flags & DMPC_PLAIN) ? 1 : 0);
   d.lpt = (c->flags & DMPC_LPT) ? 1 : 0;
   d.waves_per_simd = 1;
   d.grid_mode = 0;
@@ -1377,19 +1821,36 @@ int launch_forward(dmpc_handle h, const dmpc_config* cfg, KArgs A, const int32_t
   int launches = 0;
   if (c.plain && !A.has_lin)
     return fail(h, DMPC_EWORKSPACE, "the per-launch form needs a workspace sized with DMPC_PLAIN or DMPC_TUNED");
+  if (c.plain == 2 && !A.ws.elem)
+    return fail(h, DMPC_EWORKSPACE, "the time-parallel Riccati needs a workspace sized with DMPC_TPAR");
   if (c.plain) {
     const long long units = (long long)cfg->B * cfg->T_max;
     const int lin_grid = (int)((units + 3) / 4);
+    A.tpar = (c.plain == 2) ? 1 : 0;
+    int levels = 0;
+    while ((1 << levels) < cfg->T_max) ++levels;
     k_plain_init<<<nq, 64, 0, s>>>(A);
     ++launches;
     for (int k = 0; k < cfg->max_iter; ++k) {
       k_plain_lin<<<lin_grid, 64, 0, s>>>(A, 0);
+      ++launches;
+      if (A.tpar) {
+        const unsigned ug = (unsigned)units;
+        if (dense) k_tpar_elem<true><<<ug, 64, 0, s>>>(A);
+        else k_tpar_elem<false><<<ug, 64, 0, s>>>(A);
+        int src = 0;
+        for (int lv = 0; lv < levels; ++lv, src = 1 - src) k_tpar_scan<<<ug, 64, 0, s>>>(A, 1 << lv, src);
+        if (dense) k_tpar_gains<true><<<ug, 64, 0, s>>>(A, src);
+        else k_tpar_gains<false><<<ug, 64, 0, s>>>(A, src);
+        launches += levels + 2;
+      }
       if (dense) k_plain_riccati<true, 0><<<nq, 64, 0, s>>>(A);
       else k_plain_riccati<false, 0><<<nq, 64, 0, s>>>(A);
       if (dense) k_plain_ls<true><<<nq, 64, 0, s>>>(A);
       else k_plain_ls<false><<<nq, 64, 0, s>>>(A);
-      launches += 3;
+      launches += 2;
     }
+    A.tpar = 0;
     if (A.need_grad) {
       k_plain_lin<<<lin_grid, 64, 0, s>>>(A, 1);
       if (A.ckpt > 0) {
@@ -1505,9 +1966,11 @@ int dmpc_autotune(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, c
   dmpc_launch_choice best = default_choice(cfg);
   best.ms = 0.f;
   if (cfg->B > 0) {
-    // candidates: per-launch form; persistent form x occupancy target x grid x order
+    // candidates: per-launch form (and its time-parallel variant when the
+    // workspace has room for it); persistent form x occupancy target x grid x order
     std::vector<dmpc_launch_choice> cand;
     if (A.has_lin) cand.push_back(dmpc_launch_choice{1, 0, 1, 0, 0.f});
+    if (A.ws.elem) cand.push_back(dmpc_launch_choice{2, 0, 1, 0, 0.f});
     for (int occ = 1; occ <= 2; ++occ)
       for (int grid = 0; grid <= 1; ++grid)
         for (int lpt = 0; lpt <= (T ? 1 : 0); ++lpt) cand.push_back(dmpc_launch_choice{0, lpt, occ, grid, 0.f});
@@ -1555,7 +2018,7 @@ int dmpc_set_tuned(dmpc_handle h, const dmpc_config* cfg, int has_T, const dmpc_
   if (!h || !choice) return fail(h, DMPC_EINVAL, "NULL argument");
   int rc = check_cfg(cfg);
   if (rc) return fail(h, rc, "invalid configuration");
-  if (choice->plain < 0 || choice->plain > 1 || choice->lpt < 0 || choice->lpt > 1 || choice->waves_per_simd < 1 ||
+  if (choice->plain < 0 || choice->plain > 2 || choice->lpt < 0 || choice->lpt > 1 || choice->waves_per_simd < 1 ||
       choice->waves_per_simd > 2 || choice->grid_mode < 0 || choice->grid_mode > 1)
     return fail(h, DMPC_EINVAL, "launch choice out of range");
   h->tuned[shape_key(cfg, has_T != 0)] = *choice;

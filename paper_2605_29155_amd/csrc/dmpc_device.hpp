@@ -26,6 +26,7 @@ constexpr int SW = 8;       // per-instance state words
 
 // per-instance state words
 constexpr int S_NOM = 0, S_ITERS = 1, S_STATUS = 2, S_DONE = 3, S_T = 4;
+constexpr int S_FB = 5;  // time-parallel Riccati: a stage's clamp pattern differed from the assumed one
 
 constexpr uint32_t ST_CONVERGED = 0x1u, ST_MAXITER = 0x2u, ST_NONFINITE = 0x4u, ST_FP64 = 0x8u,
                    ST_QPMAXITER = 0x10u, ST_REGULARIZED = 0x20u;

@@ -8,7 +8,7 @@ dmpc_mpc_step (one RK4 step of the model with u*_0, and the shift).  The
 plant is the quadrotor model itself; a caller with a real plant reads
 `u_applied` and writes the measured state into `x` before the next step.
 """
-from . import (COST_DIAG, LPT, NU, NX, PLAIN, DMPCError, Handle, alloc_workspace, capture_begin, capture_end,
+from . import (COST_DIAG, LPT, NU, NX, PLAIN, TPAR, DMPCError, Handle, alloc_workspace, capture_begin, capture_end,
                forward_raw, graph_destroy, graph_launch, make_config, mpc_step, quad_params)
 
 
@@ -21,11 +21,11 @@ class RecedingHorizon:
     iterations.  State, solution and warm start stay on the device."""
 
     def __init__(self, params, B, T_max, max_iter=5, tol_du=0.0, cost_kind=COST_DIAG, warm=True, lpt=True,
-                 plain=False, fp64_pivot=1e-6, device=0, handle=None):
+                 plain=False, tpar=False, fp64_pivot=1e-6, device=0, handle=None):
         import torch
         self.handle = handle if handle is not None else Handle(device)
         self.params = quad_params(params) if isinstance(params, dict) else params
-        flags = (LPT if lpt else 0) | (PLAIN if plain else 0)
+        flags = (LPT if lpt else 0) | (PLAIN if plain else 0) | (TPAR if tpar else 0)
         self.cfg = make_config(B, T_max, cost_kind, max_iter, tol_du, flags, fp64_pivot)
         self.warm = warm
         dev = torch.device("cuda", device)
