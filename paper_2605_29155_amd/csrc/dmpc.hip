@@ -660,16 +660,25 @@ __device__ __forceinline__ int ls_select(float J, float dm, float& dsel) {
 }
 
 // writes u_out / x_out (zeros past T_b) from the nominal slot
+// (the 16 lanes take the stage entries in turn, eight loads in flight before
+// their stores: the outputs may alias nothing, but the compiler cannot know)
 __device__ void grp_outputs(const KArgs& A, const Grp& G, int n) {
-  const int b = G.b;
-  for (int t = 0; t < A.Tm; ++t) {
-    const float* zp = traj_at(A, b, n, t);
-    for (int e = G.l; e < NZ; e += 16) {
-      const float v = (t < G.T) ? zp[e < NX ? e : e + 3] : 0.f;
+  const int b = G.b, total = A.Tm * NZ;
+  for (int i0 = G.l; i0 < total; i0 += 16 * 8) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = i0 + 16 * j, t = i / NZ, e = i % NZ;
+      v[j] = (i < total && t < G.T) ? traj_at(A, b, n, t)[e < NX ? e : e + 3] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = i0 + 16 * j, t = i / NZ, e = i % NZ;
+      if (i >= total) break;
       if (e < NX) {
-        if (A.x_out) A.x_out[((size_t)b * A.Tm + t) * NX + e] = v;
+        if (A.x_out) A.x_out[((size_t)b * A.Tm + t) * NX + e] = v[j];
       } else {
-        A.u_out[((size_t)b * A.Tm + t) * NU + (e - NX)] = v;
+        A.u_out[((size_t)b * A.Tm + t) * NU + (e - NX)] = v[j];
       }
     }
   }
@@ -786,8 +795,22 @@ __global__ __launch_bounds__(64) void k_plain_init(KArgs A) {
   if (G.T > 0) grp_init(A, G);
   grp_write_state(A, G, 0, 0, 0u, G.T > 0 ? 0 : 1);
   if (A.tpar) {
+    // first pattern guess: a control of U^0 equal to a bound is clamped there
+    // (a shifted warm start keeps the clamps of the solution it came from)
+    mem_fence_wg();
     if (l == 0) A.ws.state[(size_t)G.b * SW + S_FB] = 0;
-    for (int t = l; t < A.Tm; t += 16) A.ws.pat[(size_t)G.b * A.Tm + t] = 0;
+    for (int t = l; t < A.Tm; t += 16) {
+      unsigned code = 0;
+      if (t < G.T) {
+        const float* zp = traj_at(A, G.b, 0, t);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const float u = zp[16 + a];
+          code |= (u == G.lo[a] ? 1u : (u == G.hi[a] ? 2u : 0u)) << (2 * a);
+        }
+      }
+      A.ws.pat[(size_t)G.b * A.Tm + t] = (uint8_t)code;
+    }
   }
 }
 
@@ -917,9 +940,11 @@ __device__ __forceinline__ double* elem_at(const KArgs& A, int buf, int b, int t
   return A.ws.elem + (((size_t)buf * A.B + b) * A.Tm + t) * EL_W;
 }
 
-// out = op(X) op(Y) for 13 x 13 row-major matrices in LDS (tX / tY transpose)
+// out = op(X) op(Y) for 13 x 13 row-major matrices in LDS (tX / tY
+// transpose); one output per thread of a 256-thread block
 __device__ __forceinline__ void lds_mm(double* out, const double* X, const double* Y, bool tX, bool tY) {
-  for (int idx = threadIdx.x; idx < 169; idx += 64) {
+  const int idx = threadIdx.x;
+  if (idx < 169) {
     const int r = idx / 13, c = idx % 13;
     double s = 0.0;
 #pragma unroll
@@ -1003,13 +1028,15 @@ __device__ __forceinline__ void load_F(const KArgs& A, int b, int t, double* F) 
   __syncthreads();
 }
 
+// tail != 0: the fixed-mask problem at the solution (controls equal to a bound
+// held there), for every instance whether it has converged or not
 template <bool DENSE>
-__global__ __launch_bounds__(64) void k_tpar_elem(KArgs A) {
+__global__ __launch_bounds__(64) void k_tpar_elem(KArgs A, int tail) {
   __shared__ double C[NZ * NZ], F[NX * NZ], g[NZ], T1[NX * 4], W[NX * 4];
   const int unit = blockIdx.x, b = unit / A.Tm, t = unit % A.Tm;
   const int* s = A.ws.state + (size_t)b * SW;
   const int T = s[S_T];
-  if (t >= T || s[S_DONE]) return;
+  if (t >= T || (!tail && s[S_DONE])) return;
   const size_t srow = (size_t)b * A.Tm + t;
   const int n = s[S_NOM];
   float zb[NZ];
@@ -1018,7 +1045,16 @@ __global__ __launch_bounds__(64) void k_tpar_elem(KArgs A) {
   stage_cost_lds<DENSE>(A, srow, zb, C, g);
   if (!term) load_F(A, b, t, F);
   // assumed pattern: free, or clamped at the lower / upper bound
-  const unsigned code = A.ws.pat[srow];
+  unsigned code = 0;
+  if (tail) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const float u = zb[NX + a];
+      code |= (u == A.lo[(size_t)b * 4 + a] ? 1u : (u == A.hi[(size_t)b * 4 + a] ? 2u : 0u)) << (2 * a);
+    }
+  } else {
+    code = A.ws.pat[srow];
+  }
   bool fr[4];
   double kc[4];
 #pragma unroll
@@ -1101,31 +1137,32 @@ __global__ __launch_bounds__(64) void k_tpar_elem(KArgs A) {
   }
 }
 
-// one level of the suffix scan: out[t] = in[t] (x) in[t + step] (or in[t])
-__global__ __launch_bounds__(64) void k_tpar_scan(KArgs A, int step, int src) {
+// one level of the suffix scan: out[t] = in[t] (x) in[t + step] (or in[t]);
+// one 256-thread block per (instance, stage)
+__global__ __launch_bounds__(256) void k_tpar_scan(KArgs A, int step, int src, int tail) {
   __shared__ double Ai[169], Ci[169], Ji[169], Aj[169], Cj[169], Jj[169], bi[13], ei[13], bj[13], ej[13];
-  __shared__ double Aug[13 * 26], X1[169], X2[169], v1[13], v2[13], fac[13];
+  __shared__ double G0[13 * 26], G1[13 * 26], X1[169], X2[169], X3[169], v1[13], v2[13];
+  const int tid = threadIdx.x;
   const int unit = blockIdx.x, b = unit / A.Tm, t = unit % A.Tm;
   const int* s = A.ws.state + (size_t)b * SW;
   const int T = s[S_T];
-  if (t >= T || s[S_DONE]) return;
+  if (t >= T || (!tail && s[S_DONE])) return;
   const double* ein = elem_at(A, src, b, t);
   double* eout = elem_at(A, 1 - src, b, t);
   if (t + step >= T) {
-    for (int k = threadIdx.x; k < EL_W; k += 64) eout[k] = ein[k];
+    for (int k = tid; k < EL_W; k += 256) eout[k] = ein[k];
     return;
   }
   const double* ejn = elem_at(A, src, b, t + step);
-  for (int k = threadIdx.x; k < 169; k += 64) {
-    Ai[k] = ein[EL_A + k];
-    Ci[k] = ein[EL_C + k];
-    Ji[k] = ein[EL_J + k];
-    Aj[k] = ejn[EL_A + k];
-    Cj[k] = ejn[EL_C + k];
-    Jj[k] = ejn[EL_J + k];
-  }
-  if (threadIdx.x < 13) {
-    const int k = threadIdx.x;
+  if (tid < 169) {
+    Ai[tid] = ein[EL_A + tid];
+    Ci[tid] = ein[EL_C + tid];
+    Ji[tid] = ein[EL_J + tid];
+    Aj[tid] = ejn[EL_A + tid];
+    Cj[tid] = ejn[EL_C + tid];
+    Jj[tid] = ejn[EL_J + tid];
+  } else if (tid < 169 + 13) {
+    const int k = tid - 169;
     bi[k] = ein[EL_B + k];
     ei[k] = ein[EL_E + k];
     bj[k] = ejn[EL_B + k];
@@ -1134,82 +1171,75 @@ __global__ __launch_bounds__(64) void k_tpar_scan(KArgs A, int step, int src) {
   __syncthreads();
   // [M | I] with M = I + C_i J_j
   lds_mm(X1, Ci, Jj, false, false);
-  for (int idx = threadIdx.x; idx < 13 * 26; idx += 64) {
+  for (int idx = tid; idx < 13 * 26; idx += 256) {
     const int r = idx / 26, c = idx % 26;
-    Aug[idx] = (c < 13) ? X1[r * 13 + c] + (r == c ? 1.0 : 0.0) : ((c - 13) == r ? 1.0 : 0.0);
+    G0[idx] = (c < 13) ? X1[r * 13 + c] + (r == c ? 1.0 : 0.0) : ((c - 13) == r ? 1.0 : 0.0);
   }
   __syncthreads();
-  // Gauss-Jordan with partial pivoting: Aug -> [I | M^-1]
+  // Gauss-Jordan with partial pivoting, ping-pong between G0 and G1: the
+  // pivot row (old row p, scaled) goes to row k, old row k to row p.  Every
+  // thread finds the pivot itself from column k (broadcast LDS reads), so a
+  // step needs one barrier.
+  double* S = G0;
+  double* D = G1;
   for (int k = 0; k < 13; ++k) {
-    // pivot: largest |M[r][k]| over r >= k, by a reduction over the first 16 lanes
-    double best = (threadIdx.x >= k && threadIdx.x < 13) ? fabs(Aug[threadIdx.x * 26 + k]) : -1.0;
-    int arg = threadIdx.x;
+    int p = k;
+    double best = fabs(S[k * 26 + k]);
 #pragma unroll
-    for (int off = 8; off >= 1; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 16);
-      const int oa = __shfl_xor(arg, off, 16);
-      if (ob > best || (ob == best && oa < arg)) {
-        best = ob;
-        arg = oa;
-      }
+    for (int r = 1; r < 13; ++r) {
+      const double a = fabs(S[r * 26 + k]);
+      const bool take = (r > k) && (a > best);
+      best = take ? a : best;
+      p = take ? r : p;
     }
-    const int p = __shfl(arg, 0, 64);
-    if (p != k && threadIdx.x < 26) {
-      const int c = threadIdx.x;
-      const double tmp = Aug[k * 26 + c];
-      Aug[k * 26 + c] = Aug[p * 26 + c];
-      Aug[p * 26 + c] = tmp;
-    }
-    __syncthreads();
-    const double ip = 1.0 / Aug[k * 26 + k];
-    if (threadIdx.x < 13) fac[threadIdx.x] = Aug[threadIdx.x * 26 + k];
-    __syncthreads();
-    if (threadIdx.x < 26) Aug[k * 26 + threadIdx.x] *= ip;
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < 13 * 26; idx += 64) {
+    const double ip = rcp_nr(S[p * 26 + k]);
+    for (int idx = tid; idx < 13 * 26; idx += 256) {
       const int r = idx / 26, c = idx % 26;
-      if (r != k) Aug[idx] = fma(-fac[r], Aug[k * 26 + c], Aug[idx]);
+      const double pr = S[p * 26 + c] * ip;
+      const int rr = (r == p) ? k : r;
+      D[idx] = (r == k) ? pr : fma(-S[rr * 26 + k], pr, S[rr * 26 + c]);
     }
     __syncthreads();
+    double* tmp = S;
+    S = D;
+    D = tmp;
   }
   // X2 = M^-1
-  for (int idx = threadIdx.x; idx < 169; idx += 64) X2[idx] = Aug[(idx / 13) * 26 + 13 + idx % 13];
+  if (tid < 169) X2[tid] = S[(tid / 13) * 26 + 13 + tid % 13];
   __syncthreads();
   // b = A_j M^-1 (b_i + C_i eta_j) + b_j
   lds_mv(v1, Ci, ej, false);
-  if (threadIdx.x < 13) v1[threadIdx.x] += bi[threadIdx.x];
+  if (tid < 13) v1[tid] += bi[tid];
   __syncthreads();
   lds_mv(v2, X2, v1, false);
   lds_mv(v1, Aj, v2, false);
-  if (threadIdx.x < 13) eout[EL_B + threadIdx.x] = v1[threadIdx.x] + bj[threadIdx.x];
+  if (tid < 13) eout[EL_B + tid] = v1[tid] + bj[tid];
   // eta = A_i^T M^-T (eta_j - J_j b_i) + eta_i
   lds_mv(v1, Jj, bi, false);
-  if (threadIdx.x < 13) v1[threadIdx.x] = ej[threadIdx.x] - v1[threadIdx.x];
+  if (tid < 13) v1[tid] = ej[tid] - v1[tid];
   __syncthreads();
   lds_mv(v2, X2, v1, true);
   lds_mv(v1, Ai, v2, true);
-  if (threadIdx.x < 13) eout[EL_E + threadIdx.x] = v1[threadIdx.x] + ei[threadIdx.x];
+  if (tid < 13) eout[EL_E + tid] = v1[tid] + ei[tid];
   // A = A_j M^-1 A_i
-  lds_mm(X1, X2, Ai, false, false);  // M^-1 A_i
-  lds_mm(Aug, Aj, X1, false, false); // (Aug reused as a 13 x 13 buffer)
-  for (int k = threadIdx.x; k < 169; k += 64) eout[EL_A + k] = Aug[k];
-  __syncthreads();
+  lds_mm(X1, X2, Ai, false, false);
+  lds_mm(X3, Aj, X1, false, false);
+  if (tid < 169) eout[EL_A + tid] = X3[tid];
   // C = A_j M^-1 C_i A_j^T + C_j (symmetrised)
   lds_mm(X1, X2, Ci, false, false);
-  lds_mm(Aug, Aj, X1, false, false);
-  lds_mm(X1, Aug, Aj, false, true);
-  for (int k = threadIdx.x; k < 169; k += 64) {
-    const int r = k / 13, c = k % 13;
-    eout[EL_C + k] = 0.5 * (X1[k] + X1[c * 13 + r]) + Cj[k];
+  lds_mm(X3, Aj, X1, false, false);
+  lds_mm(X1, X3, Aj, false, true);
+  if (tid < 169) {
+    const int r = tid / 13, c = tid % 13;
+    eout[EL_C + tid] = 0.5 * (X1[tid] + X1[c * 13 + r]) + Cj[tid];
   }
-  __syncthreads();
   // J = A_i^T M^-T J_j A_i + J_i (symmetrised)
-  lds_mm(X1, Jj, Ai, false, false);   // J_j A_i
-  lds_mm(Aug, X2, X1, true, false);   // M^-T J_j A_i
-  lds_mm(X1, Ai, Aug, true, false);   // A_i^T M^-T J_j A_i
-  for (int k = threadIdx.x; k < 169; k += 64) {
-    const int r = k / 13, c = k % 13;
-    eout[EL_J + k] = 0.5 * (X1[k] + X1[c * 13 + r]) + Ji[k];
+  lds_mm(X3, Jj, Ai, false, false);  // J_j A_i
+  lds_mm(X1, X2, X3, true, false);   // M^-T J_j A_i
+  lds_mm(X3, Ai, X1, true, false);   // A_i^T M^-T J_j A_i
+  if (tid < 169) {
+    const int r = tid / 13, c = tid % 13;
+    eout[EL_J + tid] = 0.5 * (X3[tid] + X3[c * 13 + r]) + Ji[tid];
   }
 }
 
@@ -1303,6 +1333,88 @@ __global__ __launch_bounds__(64) void k_tpar_gains(KArgs A, int src) {
     A.ws.pat[srow] = (uint8_t)code;
     if (st) atomicOr(&s[S_STATUS], (int)st);
   }
+}
+
+// forward tail from the scanned value functions: the stage factors the
+// backward reads (F, K, masked inverse of the free control block), with the
+// controls that equal a bound held fixed, as the serial tail sweep stores them
+template <bool DENSE>
+__global__ __launch_bounds__(64) void k_tpar_tail(KArgs A, int src) {
+  __shared__ double C[NZ * NZ], F[NX * NZ], g[NZ], V[169], Y[NX * NZ], Q[NZ * NZ];
+  const int unit = blockIdx.x, b = unit / A.Tm, t = unit % A.Tm;
+  int* s = A.ws.state + (size_t)b * SW;
+  const int T = s[S_T];
+  if (t >= T) return;
+  const int n = s[S_NOM];
+  const size_t srow = (size_t)b * A.Tm + t;
+  float zb[NZ];
+  load_z(traj_at(A, b, n, t), zb);
+  stage_cost_lds<DENSE>(A, srow, zb, C, g);
+  const bool has_dyn = (t + 1 < T);
+  if (has_dyn) {
+    load_F(A, b, t, F);
+    const double* E = elem_at(A, src, b, t + 1);
+    for (int k = threadIdx.x; k < 169; k += 64) V[k] = E[EL_J + k];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NX * NZ; idx += 64) {
+      const int r = idx / NZ, c = idx % NZ;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < NX; ++k) acc = fma(V[r * 13 + k], F[k * NZ + c], acc);
+      Y[idx] = acc;
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < NZ * NZ; idx += 64) {
+    const int r = idx / NZ, c = idx % NZ;
+    double acc = C[idx];
+    if (has_dyn) {
+#pragma unroll
+      for (int k = 0; k < NX; ++k) acc = fma(F[k * NZ + r], Y[k * NZ + c], acc);
+    }
+    Q[idx] = acc;
+  }
+  __syncthreads();
+  double H[16], fr[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) H[a * 4 + bb] = 0.5 * (Q[(NX + a) * NZ + NX + bb] + Q[(NX + bb) * NZ + NX + a]);
+    const float u = zb[NX + a];
+    fr[a] = (u == A.lo[(size_t)b * 4 + a] || u == A.hi[(size_t)b * 4 + a]) ? 0.0 : 1.0;
+  }
+  Chol4 Ch;
+  uint32_t st = 0;
+  chol4(H, fr, A.piv, Ch, st);
+  float* tp = tail_at(A, b, t);
+  for (int idx = threadIdx.x; idx < NZ * NX; idx += 64) {
+    const int c = idx / NX, r = idx % NX;
+    tp[c * 16 + r] = has_dyn ? (float)F[r * NZ + c] : 0.f;
+  }
+  if (threadIdx.x < NX) {
+    const int c = threadIdx.x;
+    double Kd[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) Kd[a] = fr[a] * 0.5 * (Q[(NX + a) * NZ + c] + Q[c * NZ + NX + a]);
+    solve4(Ch, Kd);
+    *(float4*)(tp + FS + c * 4) = make_float4((float)(-Kd[0]), (float)(-Kd[1]), (float)(-Kd[2]), (float)(-Kd[3]));
+  }
+  if (threadIdx.x == NX) {
+    double M[16];
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+      double e[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) e[a] = (a == bb) ? fr[bb] : 0.0;
+      solve4(Ch, e);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) M[a * 4 + bb] = fr[a] * e[a];
+    }
+    double* mp = (double*)(tp + FS + 52);
+#pragma unroll
+    for (int i = 0; i < 16; i += 2) *(double2*)(mp + i) = make_double2(M[i], M[i + 1]);
+  }
+  if (threadIdx.x == 0 && st) atomicOr(&s[S_STATUS], (int)st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1565,40 +1677,36 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
 // ---------------------------------------------------------------------------
 // receding horizon (Alg. 1 outer loop): apply u*_0 to the state with one RK4
 // step of the model, and shift the solution by one stage for the next solve's
-// warm start (the last stage repeats).  One thread per instance; u_warm may
-// be the same buffer as u_star (each thread reads stage t + 1 before it
-// writes stage t).
+// warm start (the last stage repeats).  One 64-thread block per instance: the
+// instance's controls are staged in LDS before any is written, so u_warm may
+// be the same buffer as u_star.
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(64) void k_mpc_step(Dyn P, int B, int Tm, const int* Tarr, float* xs, const float* us,
                                                  float* uw, float* ua) {
-  const int b = blockIdx.x * 64 + threadIdx.x;
-  if (b >= B) return;
+  __shared__ float ur[DMPC_T_LIMIT * NU];
+  const int b = blockIdx.x, tid = threadIdx.x;
   int T = Tarr ? Tarr[b] : Tm;
   T = T < 0 ? 0 : (T > Tm ? Tm : T);
-  float u0[NU] = {0.f, 0.f, 0.f, 0.f};
-  if (T > 0) {
+  const float* row = us + (size_t)b * Tm * NU;
+  for (int i = tid; i < T * NU; i += 64) ur[i] = row[i];
+  __syncthreads();
+  if (tid == 0 && T > 0) {
+    float x[NX], xn[NX], u0[NU];
 #pragma unroll
-    for (int a = 0; a < NU; ++a) u0[a] = us[(size_t)b * Tm * NU + a];
-    float x[NX], xn[NX];
+    for (int a = 0; a < NU; ++a) u0[a] = ur[a];
 #pragma unroll
     for (int i = 0; i < NX; ++i) x[i] = xs[(size_t)b * NX + i];
     rk4(P, x, u0, xn);
 #pragma unroll
     for (int i = 0; i < NX; ++i) xs[(size_t)b * NX + i] = xn[i];
   }
-  if (ua) {
-#pragma unroll
-    for (int a = 0; a < NU; ++a) ua[(size_t)b * NU + a] = u0[a];
-  }
+  if (ua && tid < NU) ua[(size_t)b * NU + tid] = (T > 0) ? ur[tid] : 0.f;
   if (uw) {
-    for (int t = 0; t < Tm; ++t) {
+    for (int i = tid; i < Tm * NU; i += 64) {
+      const int t = i / NU, a = i % NU;
       const int src = (t + 1 < T) ? t + 1 : T - 1;
-#pragma unroll
-      for (int a = 0; a < NU; ++a) {
-        const float v = (t < T) ? us[((size_t)b * Tm + src) * NU + a] : 0.f;
-        uw[((size_t)b * Tm + t) * NU + a] = v;
-      }
+      uw[(size_t)b * Tm * NU + i] = (t < T) ? ur[src * NU + a] : 0.f;
     }
   }
 }
@@ -1836,10 +1944,10 @@ int launch_forward(dmpc_handle h, const dmpc_config* cfg, KArgs A, const int32_t
       ++launches;
       if (A.tpar) {
         const unsigned ug = (unsigned)units;
-        if (dense) k_tpar_elem<true><<<ug, 64, 0, s>>>(A);
-        else k_tpar_elem<false><<<ug, 64, 0, s>>>(A);
+        if (dense) k_tpar_elem<true><<<ug, 64, 0, s>>>(A, 0);
+        else k_tpar_elem<false><<<ug, 64, 0, s>>>(A, 0);
         int src = 0;
-        for (int lv = 0; lv < levels; ++lv, src = 1 - src) k_tpar_scan<<<ug, 64, 0, s>>>(A, 1 << lv, src);
+        for (int lv = 0; lv < levels; ++lv, src = 1 - src) k_tpar_scan<<<ug, 256, 0, s>>>(A, 1 << lv, src, 0);
         if (dense) k_tpar_gains<true><<<ug, 64, 0, s>>>(A, src);
         else k_tpar_gains<false><<<ug, 64, 0, s>>>(A, src);
         launches += levels + 2;
@@ -1851,7 +1959,18 @@ int launch_forward(dmpc_handle h, const dmpc_config* cfg, KArgs A, const int32_t
       launches += 2;
     }
     A.tpar = 0;
-    if (A.need_grad) {
+    if (A.need_grad && c.plain == 2 && A.ckpt == 0) {
+      // the tail's fixed-mask problem through the same scan
+      const unsigned ug = (unsigned)units;
+      k_plain_lin<<<lin_grid, 64, 0, s>>>(A, 1);
+      if (dense) k_tpar_elem<true><<<ug, 64, 0, s>>>(A, 1);
+      else k_tpar_elem<false><<<ug, 64, 0, s>>>(A, 1);
+      int src = 0;
+      for (int lv = 0; lv < levels; ++lv, src = 1 - src) k_tpar_scan<<<ug, 256, 0, s>>>(A, 1 << lv, src, 1);
+      if (dense) k_tpar_tail<true><<<ug, 64, 0, s>>>(A, src);
+      else k_tpar_tail<false><<<ug, 64, 0, s>>>(A, src);
+      launches += levels + 3;
+    } else if (A.need_grad) {
       k_plain_lin<<<lin_grid, 64, 0, s>>>(A, 1);
       if (A.ckpt > 0) {
         if (dense) k_plain_riccati<true, 2><<<nq, 64, 0, s>>>(A);
@@ -2116,8 +2235,8 @@ int dmpc_mpc_step(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, c
     return fail(h, DMPC_EINVAL, "non-positive mass, inertia or step");
   rc = hip_check(h, hipSetDevice(h->device), "hipSetDevice");
   if (rc) return rc;
-  k_mpc_step<<<(cfg->B + 63) / 64, 64, 0, (hipStream_t)stream>>>(make_dyn(dyn), cfg->B, cfg->T_max, T, x_state,
-                                                                   u_star, u_warm, u_applied);
+  k_mpc_step<<<cfg->B, 64, 0, (hipStream_t)stream>>>(make_dyn(dyn), cfg->B, cfg->T_max, T, x_state, u_star, u_warm,
+                                                       u_applied);
   h->last_launches = 1;
   return hip_check(h, hipGetLastError(), "kernel launch");
 }

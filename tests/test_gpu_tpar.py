@@ -15,7 +15,8 @@ from test_gpu_parity import check_parity
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("case", ["cfg0", "cfg0_free", "hover_b1_t50", "hover_b16_t50", "ragged", "dense"])
+@pytest.mark.parametrize("case", ["cfg0", "cfg0_free", "hover_b1_t50", "hover_b16_t50", "ragged", "dense",
+                                  "ckpt"])
 def test_tpar_matches_oracle(case):
     if case == "cfg0":
         d = W.make(0)
@@ -32,9 +33,11 @@ def test_tpar_matches_oracle(case):
         d["Q"][pad] = 0
         d["p"][pad] = 0
         d["grad_u"][pad] = 0
-    else:
+    elif case == "dense":
         d = W.make(4, B=16, T=12, seed=3105)
-    g = run_gpu(d, tpar=True)
+    else:
+        d = W.make(0, B=16, T=14, pu_scale=0.01, seed=3108)
+    g = run_gpu(d, tpar=True, ckpt=4 if case == "ckpt" else 0)
     o = oracle_replay(d, g)
     check_parity(d, g, o, "tpar " + case)
 
@@ -55,7 +58,11 @@ def test_tpar_launch_structure():
     d = W.make_hover_target(2, 20, seed=3107)
     g = run_gpu(d, tpar=True)
     levels = 5  # ceil(log2 20)
-    # init; per iteration lin, elements, levels, gains, fallback sweep, line search; tail lin + sweep; outputs
+    # init; per iteration lin, elements, levels, gains, fallback sweep, line search; the tail through the
+    # same scan (lin, elements, levels, factors); outputs
+    assert g["launches_fwd"] == 1 + d["K"] * (1 + 1 + levels + 1 + 2) + (levels + 3) + 1
+    # with checkpointing the tail is the serial sweep
+    g = run_gpu(d, tpar=True, ckpt=4)
     assert g["launches_fwd"] == 1 + d["K"] * (1 + 1 + levels + 1 + 2) + 2 + 1
 
 
