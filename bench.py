@@ -223,7 +223,9 @@ def closed_loop_latency(steps=40, warmup=5):
     from the current state + apply u*_0 + shift), hover-to-target workload,
     for T 10, 20, 50: fixed K = 5, and K <= 30 stopping at ||dU||_inf < 1e-5,
     each cold (every solve from hover thrust) and warm (from the shifted
-    previous solution), the warm loop also as one captured HIP graph per step.
+    previous solution), the warm loop also as one captured HIP graph per step
+    and, warm, with the per-launch form whose backward pass is the
+    time-parallel Riccati (DMPC_TPAR).
     wall_ms: host time from the call to the step's completion (stream
     synchronised); gpu_ms: HIP events around the step on its stream.  Each
     variant runs twice, in the order cold, warm, graph and then reversed (so
@@ -238,8 +240,8 @@ def closed_loop_latency(steps=40, warmup=5):
     dev = "cuda:0"
     h = D.Handle(0)
 
-    def run(t, T, K, tol, warm, graph):
-        rh = RecedingHorizon(W.quad_params_f32(), 1, T, max_iter=K, tol_du=tol, warm=warm, handle=h)
+    def run(t, T, K, tol, warm, graph, tpar=False):
+        rh = RecedingHorizon(W.quad_params_f32(), 1, T, max_iter=K, tol_du=tol, warm=warm, handle=h, tpar=tpar)
         rh.reset(t["x0"])
         s = torch.cuda.Stream()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -268,7 +270,8 @@ def closed_loop_latency(steps=40, warmup=5):
         return wall, gpu, its, rh.x[0, :3].cpu().numpy()
 
     rows = []
-    variants = ((False, False), (True, False), (True, True))
+    variants = ((False, False, False), (True, False, False), (True, True, False), (True, False, True),
+                (True, True, True))
     for T in (10, 20, 50):
         d = W.make_hover_target(1, T)
         t = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev) for k in ("x0", "Q", "p", "lo", "hi")}
@@ -278,15 +281,17 @@ def closed_loop_latency(steps=40, warmup=5):
             for v in variants + variants[::-1]:
                 w, g, i, pos = run(t, T, K, tol, *v)
                 acc[v] = (acc[v][0] + w, acc[v][1] + g, acc[v][2] + i, pos)
-            for (warm, graph) in variants:
-                w, g, i, pos = acc[(warm, graph)]
-                row = dict(B=1, T=T, K=K, tol_du=tol, warm=warm, graph=graph, wall_ms=float(np.median(w)),
+            for (warm, graph, tpar) in variants:
+                w, g, i, pos = acc[(warm, graph, tpar)]
+                row = dict(B=1, T=T, K=K, tol_du=tol, warm=warm, graph=graph, form="tpar" if tpar else "persistent",
+                           wall_ms=float(np.median(w)),
                            wall_ms_p90=float(np.percentile(w, 90)), gpu_ms=float(np.median(g)),
                            mean_iters=float(np.mean(i)), median_iters=float(np.median(i)),
                            final_pos_err_m=float(np.linalg.norm(pos - target)))
                 rows.append(row)
-                print("closed loop T=%2d K=%2d tol=%g %-10s: wall %.3f ms (p90 %.3f), gpu %.3f ms, iterations "
-                      "mean %.1f median %.0f" % (T, K, tol, ("warm" if warm else "cold") + ("+graph" if graph else ""),
+                print("closed loop T=%2d K=%2d tol=%g %-16s: wall %.3f ms (p90 %.3f), gpu %.3f ms, iterations "
+                      "mean %.1f median %.0f" % (T, K, tol, ("warm" if warm else "cold") + ("+graph" if graph else "")
+                                                 + ("+tpar" if tpar else ""),
                                                  row["wall_ms"], row["wall_ms_p90"], row["gpu_ms"],
                                                  row["mean_iters"], row["median_iters"]), file=sys.stderr, flush=True)
     return rows
