@@ -934,6 +934,7 @@ __global__ __launch_bounds__(64) void k_plain_finalize(KArgs A) {
 // runs instead.  One wavefront per (instance, stage); FP64 throughout.
 // ---------------------------------------------------------------------------
 
+constexpr int SCAN_NT = 256;  // threads per combination
 constexpr int EL_A = 0, EL_B = 169, EL_C = 182, EL_E = 351, EL_J = 364, EL_W = 536;  // doubles per element
 
 __device__ __forceinline__ double* elem_at(const KArgs& A, int buf, int b, int t) {
@@ -941,10 +942,10 @@ __device__ __forceinline__ double* elem_at(const KArgs& A, int buf, int b, int t
 }
 
 // out = op(X) op(Y) for 13 x 13 row-major matrices in LDS (tX / tY
-// transpose); one output per thread of a 256-thread block
+// transpose), outputs spread over the NT threads of the block
+template <int NT>
 __device__ __forceinline__ void lds_mm(double* out, const double* X, const double* Y, bool tX, bool tY) {
-  const int idx = threadIdx.x;
-  if (idx < 169) {
+  for (int idx = threadIdx.x; idx < 169; idx += NT) {
     const int r = idx / 13, c = idx % 13;
     double s = 0.0;
 #pragma unroll
@@ -1138,8 +1139,9 @@ __global__ __launch_bounds__(64) void k_tpar_elem(KArgs A, int tail) {
 }
 
 // one level of the suffix scan: out[t] = in[t] (x) in[t + step] (or in[t]);
-// one 256-thread block per (instance, stage)
-__global__ __launch_bounds__(256) void k_tpar_scan(KArgs A, int step, int src, int tail) {
+// one NT-thread block per (instance, stage)
+template <int NT>
+__global__ __launch_bounds__(NT) void k_tpar_scan(KArgs A, int step, int src, int tail) {
   __shared__ double Ai[169], Ci[169], Ji[169], Aj[169], Cj[169], Jj[169], bi[13], ei[13], bj[13], ej[13];
   __shared__ double G0[13 * 26], G1[13 * 26], X1[169], X2[169], X3[169], v1[13], v2[13];
   const int tid = threadIdx.x;
@@ -1150,28 +1152,30 @@ __global__ __launch_bounds__(256) void k_tpar_scan(KArgs A, int step, int src, i
   const double* ein = elem_at(A, src, b, t);
   double* eout = elem_at(A, 1 - src, b, t);
   if (t + step >= T) {
-    for (int k = tid; k < EL_W; k += 256) eout[k] = ein[k];
+    for (int k = tid; k < EL_W; k += NT) eout[k] = ein[k];
     return;
   }
   const double* ejn = elem_at(A, src, b, t + step);
-  if (tid < 169) {
-    Ai[tid] = ein[EL_A + tid];
-    Ci[tid] = ein[EL_C + tid];
-    Ji[tid] = ein[EL_J + tid];
-    Aj[tid] = ejn[EL_A + tid];
-    Cj[tid] = ejn[EL_C + tid];
-    Jj[tid] = ejn[EL_J + tid];
-  } else if (tid < 169 + 13) {
-    const int k = tid - 169;
-    bi[k] = ein[EL_B + k];
-    ei[k] = ein[EL_E + k];
-    bj[k] = ejn[EL_B + k];
-    ej[k] = ejn[EL_E + k];
+  for (int k = tid; k < 169 + 13; k += NT) {
+    if (k < 169) {
+      Ai[k] = ein[EL_A + k];
+      Ci[k] = ein[EL_C + k];
+      Ji[k] = ein[EL_J + k];
+      Aj[k] = ejn[EL_A + k];
+      Cj[k] = ejn[EL_C + k];
+      Jj[k] = ejn[EL_J + k];
+    } else {
+      const int m = k - 169;
+      bi[m] = ein[EL_B + m];
+      ei[m] = ein[EL_E + m];
+      bj[m] = ejn[EL_B + m];
+      ej[m] = ejn[EL_E + m];
+    }
   }
   __syncthreads();
   // [M | I] with M = I + C_i J_j
-  lds_mm(X1, Ci, Jj, false, false);
-  for (int idx = tid; idx < 13 * 26; idx += 256) {
+  lds_mm<NT>(X1, Ci, Jj, false, false);
+  for (int idx = tid; idx < 13 * 26; idx += NT) {
     const int r = idx / 26, c = idx % 26;
     G0[idx] = (c < 13) ? X1[r * 13 + c] + (r == c ? 1.0 : 0.0) : ((c - 13) == r ? 1.0 : 0.0);
   }
@@ -1193,7 +1197,7 @@ __global__ __launch_bounds__(256) void k_tpar_scan(KArgs A, int step, int src, i
       p = take ? r : p;
     }
     const double ip = rcp_nr(S[p * 26 + k]);
-    for (int idx = tid; idx < 13 * 26; idx += 256) {
+    for (int idx = tid; idx < 13 * 26; idx += NT) {
       const int r = idx / 26, c = idx % 26;
       const double pr = S[p * 26 + c] * ip;
       const int rr = (r == p) ? k : r;
@@ -1205,7 +1209,7 @@ __global__ __launch_bounds__(256) void k_tpar_scan(KArgs A, int step, int src, i
     D = tmp;
   }
   // X2 = M^-1
-  if (tid < 169) X2[tid] = S[(tid / 13) * 26 + 13 + tid % 13];
+  for (int k = tid; k < 169; k += NT) X2[k] = S[(k / 13) * 26 + 13 + k % 13];
   __syncthreads();
   // b = A_j M^-1 (b_i + C_i eta_j) + b_j
   lds_mv(v1, Ci, ej, false);
@@ -1222,24 +1226,24 @@ __global__ __launch_bounds__(256) void k_tpar_scan(KArgs A, int step, int src, i
   lds_mv(v1, Ai, v2, true);
   if (tid < 13) eout[EL_E + tid] = v1[tid] + ei[tid];
   // A = A_j M^-1 A_i
-  lds_mm(X1, X2, Ai, false, false);
-  lds_mm(X3, Aj, X1, false, false);
-  if (tid < 169) eout[EL_A + tid] = X3[tid];
+  lds_mm<NT>(X1, X2, Ai, false, false);
+  lds_mm<NT>(X3, Aj, X1, false, false);
+  for (int k = tid; k < 169; k += NT) eout[EL_A + k] = X3[k];
   // C = A_j M^-1 C_i A_j^T + C_j (symmetrised)
-  lds_mm(X1, X2, Ci, false, false);
-  lds_mm(X3, Aj, X1, false, false);
-  lds_mm(X1, X3, Aj, false, true);
-  if (tid < 169) {
-    const int r = tid / 13, c = tid % 13;
-    eout[EL_C + tid] = 0.5 * (X1[tid] + X1[c * 13 + r]) + Cj[tid];
+  lds_mm<NT>(X1, X2, Ci, false, false);
+  lds_mm<NT>(X3, Aj, X1, false, false);
+  lds_mm<NT>(X1, X3, Aj, false, true);
+  for (int k = tid; k < 169; k += NT) {
+    const int r = k / 13, c = k % 13;
+    eout[EL_C + k] = 0.5 * (X1[k] + X1[c * 13 + r]) + Cj[k];
   }
   // J = A_i^T M^-T J_j A_i + J_i (symmetrised)
-  lds_mm(X3, Jj, Ai, false, false);  // J_j A_i
-  lds_mm(X1, X2, X3, true, false);   // M^-T J_j A_i
-  lds_mm(X3, Ai, X1, true, false);   // A_i^T M^-T J_j A_i
-  if (tid < 169) {
-    const int r = tid / 13, c = tid % 13;
-    eout[EL_J + tid] = 0.5 * (X3[tid] + X3[c * 13 + r]) + Ji[tid];
+  lds_mm<NT>(X3, Jj, Ai, false, false);  // J_j A_i
+  lds_mm<NT>(X1, X2, X3, true, false);   // M^-T J_j A_i
+  lds_mm<NT>(X3, Ai, X1, true, false);   // A_i^T M^-T J_j A_i
+  for (int k = tid; k < 169; k += NT) {
+    const int r = k / 13, c = k % 13;
+    eout[EL_J + k] = 0.5 * (X3[k] + X3[c * 13 + r]) + Ji[k];
   }
 }
 
@@ -1570,15 +1574,15 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
   float xt[NX];
 #pragma unroll
   for (int i = 0; i < NX; ++i) xt[i] = 0.f;
-  // gradient w.r.t. the model constants: lane j < 8 carries the sensitivities
-  // xi_j, eta_j of constant j (forward form of the two costate sums)
-  float sxi[THETA ? NX : 1], seta[THETA ? NX : 1];
+  // gradient w.r.t. the model constants (forward form of the two costate
+  // sums): lane j < 8 carries xi_j, lane 8 + j carries eta_j of constant j
+  float sv[THETA ? NX : 1];
   double gth = 0.0;
   dmpc_theta::PN PN;
   if constexpr (THETA) {
 #pragma unroll
-    for (int i = 0; i < NX; ++i) sxi[i] = seta[i] = 0.f;
-    PN = dmpc_theta::make_pn(A.raw, l < 8 ? l : 0);
+    for (int i = 0; i < NX; ++i) sv[i] = 0.f;
+    PN = dmpc_theta::make_pn(A.raw, l & 7);
   }
   FStage cf, nf;
   for (int sg = 0; sg < nseg; ++sg) {
@@ -1646,9 +1650,17 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
         }
         float dot = 0.f;
 #pragma unroll
-        for (int k = 0; k < NX; ++k) dot = fmaf(rb(ht, k), sxi[k], fmaf(rb(hs, k), seta[k], dot));
+        for (int k = 0; k < NX; ++k) {
+          // both broadcasts on every lane (a broadcast inside a lane-dependent
+          // branch would read lanes that the branch has switched off)
+          const float bt = rb(ht, k), bs = rb(hs, k);
+          dot = fmaf((l < 8) ? bt : bs, sv[k], dot);
+        }
         gth += (double)dot;
-        if (t + 1 < T && l < 8) dmpc_theta::propagate(PN, cf.zs, cf.zs + NX, xt, ut, sxi, seta);
+        if (t + 1 < T) {
+          if (l < 8) dmpc_theta::propagate_xi(PN, cf.zs, cf.zs + NX, sv);
+          else dmpc_theta::propagate_eta(PN, cf.zs, cf.zs + NX, xt, ut, sv);
+        }
       }
       if (t + 1 < T) {
         float xi = 0.f;
@@ -1670,7 +1682,8 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
     for (int m = l; m < W; m += 16) A.gQ[srow * W + m] = 0.f;
   }
   if constexpr (THETA) {
-    if (l < 8) A.gdyn[(size_t)b * 8 + l] = (float)gth;
+    const double both = gth + __shfl_xor(gth, 8, 16);  // xi part (lane j) + eta part (lane 8 + j)
+    if (l < 8) A.gdyn[(size_t)b * 8 + l] = (float)both;
   }
 }
 
@@ -1947,7 +1960,7 @@ int launch_forward(dmpc_handle h, const dmpc_config* cfg, KArgs A, const int32_t
         if (dense) k_tpar_elem<true><<<ug, 64, 0, s>>>(A, 0);
         else k_tpar_elem<false><<<ug, 64, 0, s>>>(A, 0);
         int src = 0;
-        for (int lv = 0; lv < levels; ++lv, src = 1 - src) k_tpar_scan<<<ug, 256, 0, s>>>(A, 1 << lv, src, 0);
+        for (int lv = 0; lv < levels; ++lv, src = 1 - src) k_tpar_scan<SCAN_NT><<<ug, SCAN_NT, 0, s>>>(A, 1 << lv, src, 0);
         if (dense) k_tpar_gains<true><<<ug, 64, 0, s>>>(A, src);
         else k_tpar_gains<false><<<ug, 64, 0, s>>>(A, src);
         launches += levels + 2;
@@ -1966,7 +1979,7 @@ int launch_forward(dmpc_handle h, const dmpc_config* cfg, KArgs A, const int32_t
       if (dense) k_tpar_elem<true><<<ug, 64, 0, s>>>(A, 1);
       else k_tpar_elem<false><<<ug, 64, 0, s>>>(A, 1);
       int src = 0;
-      for (int lv = 0; lv < levels; ++lv, src = 1 - src) k_tpar_scan<<<ug, 256, 0, s>>>(A, 1 << lv, src, 1);
+      for (int lv = 0; lv < levels; ++lv, src = 1 - src) k_tpar_scan<SCAN_NT><<<ug, SCAN_NT, 0, s>>>(A, 1 << lv, src, 1);
       if (dense) k_tpar_tail<true><<<ug, 64, 0, s>>>(A, src);
       else k_tpar_tail<false><<<ug, 64, 0, s>>>(A, src);
       launches += levels + 3;

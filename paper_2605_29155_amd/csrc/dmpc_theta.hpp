@@ -14,15 +14,18 @@
 // recursion of a state sensitivity: with xi_{t+1} = A_t xi_t + df/dtheta and
 // eta_{t+1} = A_t eta_t + d(F_t zt_t)/dtheta (xi_0 = eta_0 = 0),
 //   dL/dtheta = sum_t ht_t^T xi_t + hs_t^T eta_t,
-// which needs no backward pass and no storage.  Lane j < 8 of an instance
-// owns constant j: it evaluates one RK4 step in a five-part number
-//   v + e eps + d del + ed eps del + s sig
-// with the state seeded (x*, xt, 0, eta_j, xi_j), the controls (u*, ut, 0, 0,
-// 0) and constant j seeded with del = sig = 1.  The sig part of the result is
-// xi_{t+1} (first order in sig: A xi + df/dtheta_j) and the eps-del part is
-// eta_{t+1} (A eta + d(F zt)/dtheta_j; the state carries no del part, so no
-// second derivative in the state enters).  Products of sig with eps or del
-// are not tracked.
+// which needs no backward pass and no storage.  Constant j is owned by two
+// lanes of the instance's row, each taking one RK4 step per stage in its own
+// number type:
+//  * lane j carries xi_j in dual numbers v + s sig, state seeded (x*, xi_j),
+//    constant j seeded with sig: the sig part of the step is A xi_j +
+//    df/dtheta_j = xi_{t+1};
+//  * lane 8 + j carries eta_j in numbers v + e eps + d del + ed eps del,
+//    state seeded (x*, xt, 0, eta_j), controls (u*, ut, 0, 0), constant j
+//    seeded with del: the eps-del part is A eta_j + d(F zt)/dtheta_j =
+//    eta_{t+1} (the state carries no del part, so no second derivative in
+//    the state enters).
+// The constants themselves are pairs (value, derivative along constant j).
 #pragma once
 
 namespace dmpc_theta {
@@ -30,39 +33,59 @@ namespace dmpc_theta {
 using dmpc_dev::NU;
 using dmpc_dev::NX;
 
-struct N5 {
-  float v, e, d, ed, s;
+// a model constant (or a function of them) and its derivative along constant j
+struct P2 {
+  float v, d;
 };
+__device__ __forceinline__ P2 operator+(const P2& a, const P2& b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ P2 operator-(const P2& a, const P2& b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ P2 operator*(float c, const P2& a) { return {c * a.v, c * a.d}; }
+__device__ __forceinline__ P2 operator*(const P2& a, const P2& b) { return {a.v * b.v, fmaf(a.v, b.d, a.d * b.v)}; }
+__device__ __forceinline__ P2 inv(const P2& a) {
+  const float r = 1.f / a.v;
+  return {r, -a.d * r * r};
+}
 
-__device__ __forceinline__ N5 cst(float v) { return {v, 0.f, 0.f, 0.f, 0.f}; }
-__device__ __forceinline__ N5 operator+(const N5& a, const N5& b) {
-  return {a.v + b.v, a.e + b.e, a.d + b.d, a.ed + b.ed, a.s + b.s};
-}
-__device__ __forceinline__ N5 operator-(const N5& a, const N5& b) {
-  return {a.v - b.v, a.e - b.e, a.d - b.d, a.ed - b.ed, a.s - b.s};
-}
-__device__ __forceinline__ N5 operator-(const N5& a) { return {-a.v, -a.e, -a.d, -a.ed, -a.s}; }
-__device__ __forceinline__ N5 operator*(float c, const N5& a) { return {c * a.v, c * a.e, c * a.d, c * a.ed, c * a.s}; }
-__device__ __forceinline__ N5 operator*(const N5& a, const N5& b) {
+// dual number for xi: value and derivative along constant j
+struct D2 {
+  float v, s;
+};
+__device__ __forceinline__ D2 lift(const P2& p, D2*) { return {p.v, p.d}; }
+__device__ __forceinline__ D2 operator+(const D2& a, const D2& b) { return {a.v + b.v, a.s + b.s}; }
+__device__ __forceinline__ D2 operator-(const D2& a, const D2& b) { return {a.v - b.v, a.s - b.s}; }
+__device__ __forceinline__ D2 operator-(const D2& a) { return {-a.v, -a.s}; }
+__device__ __forceinline__ D2 operator*(float c, const D2& a) { return {c * a.v, c * a.s}; }
+__device__ __forceinline__ D2 operator*(const D2& a, const D2& b) { return {a.v * b.v, fmaf(a.v, b.s, a.s * b.v)}; }
+__device__ __forceinline__ D2 operator*(const D2& a, const P2& b) { return {a.v * b.v, fmaf(a.v, b.d, a.s * b.v)}; }
+
+// hyper-dual number for eta: value, tangent along the adjoint solution,
+// derivative along constant j, mixed part
+struct H4 {
+  float v, e, d, ed;
+};
+__device__ __forceinline__ H4 lift(const P2& p, H4*) { return {p.v, 0.f, p.d, 0.f}; }
+__device__ __forceinline__ H4 operator+(const H4& a, const H4& b) { return {a.v + b.v, a.e + b.e, a.d + b.d, a.ed + b.ed}; }
+__device__ __forceinline__ H4 operator-(const H4& a, const H4& b) { return {a.v - b.v, a.e - b.e, a.d - b.d, a.ed - b.ed}; }
+__device__ __forceinline__ H4 operator-(const H4& a) { return {-a.v, -a.e, -a.d, -a.ed}; }
+__device__ __forceinline__ H4 operator*(float c, const H4& a) { return {c * a.v, c * a.e, c * a.d, c * a.ed}; }
+__device__ __forceinline__ H4 operator*(const H4& a, const H4& b) {
   return {a.v * b.v, fmaf(a.v, b.e, a.e * b.v), fmaf(a.v, b.d, a.d * b.v),
-          fmaf(a.v, b.ed, fmaf(a.e, b.d, fmaf(a.d, b.e, a.ed * b.v))), fmaf(a.v, b.s, a.s * b.v)};
+          fmaf(a.v, b.ed, fmaf(a.e, b.d, fmaf(a.d, b.e, a.ed * b.v)))};
 }
-// 1 / a: r - r^2 (e eps + d del + s sig) + (2 r^3 e d - r^2 ed) eps del
-__device__ __forceinline__ N5 inv(const N5& a) {
-  const float r = 1.f / a.v, r2 = r * r;
-  return {r, -a.e * r2, -a.d * r2, r2 * (2.f * r * a.e * a.d - a.ed), -a.s * r2};
+__device__ __forceinline__ H4 operator*(const H4& a, const P2& b) {
+  return {a.v * b.v, a.e * b.v, fmaf(a.v, b.d, a.d * b.v), fmaf(a.e, b.d, a.ed * b.v)};
 }
 
-// model constants as five-part numbers, constant j seeded
+// model constants as pairs, constant j seeded
 struct PN {
-  N5 im, a, kappa, iJx, iJy, iJz, cx, cy, cz, h, g;
+  P2 im, a, kappa, iJx, iJy, iJz, cx, cy, cz, h, h2, h6, g;
 };
 
 __device__ __forceinline__ PN make_pn(const dmpc_quad_params& q, int j) {
   const float raw[8] = {q.mass, q.Jxx, q.Jyy, q.Jzz, q.arm, q.kappa, q.dt, q.g};
-  N5 th[8];
+  P2 th[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) th[i] = {raw[i], 0.f, (i == j) ? 1.f : 0.f, 0.f, (i == j) ? 1.f : 0.f};
+  for (int i = 0; i < 8; ++i) th[i] = {raw[i], (i == j) ? 1.f : 0.f};
   PN P;
   P.im = inv(th[0]);
   P.a = 0.70710678118654752f * th[4];
@@ -74,75 +97,97 @@ __device__ __forceinline__ PN make_pn(const dmpc_quad_params& q, int j) {
   P.cy = (th[1] - th[3]) * P.iJy;  // (Jxx - Jzz) / Jyy
   P.cz = (th[2] - th[1]) * P.iJz;  // (Jyy - Jxx) / Jzz
   P.h = th[6];
+  P.h2 = 0.5f * th[6];
+  P.h6 = (1.f / 6.f) * th[6];
   P.g = th[7];
   return P;
 }
 
-// right-hand side of eq. (1) for the X-configuration quadrotor (rotor i at
-// pi/4 + i pi/2, spin signs +,-,+,-; scalar-first quaternion, body rates)
-__device__ __forceinline__ void rhs5(const PN& P, const N5* x, const N5& s, const N5& tx, const N5& ty, const N5& tz,
-                                     N5* o) {
-  const N5 qw = x[3], qx = x[4], qy = x[5], qz = x[6], wx = x[10], wy = x[11], wz = x[12];
-  o[0] = x[7];
-  o[1] = x[8];
-  o[2] = x[9];
+// derivatives of the rotational and velocity states (eq. (1), X-configuration
+// quadrotor, scalar-first quaternion, body rates); the position derivative is
+// the velocity itself and is taken by the caller.  x holds q (3..6), v (7..9)
+// and w (10..12) at their usual indices.
+template <class N>
+__device__ __forceinline__ void rhs_qvw(const PN& P, const N* x, const N& s, const N& tx, const N& ty, const N& tz,
+                                        N* o) {
+  const N qw = x[3], qx = x[4], qy = x[5], qz = x[6], wx = x[10], wy = x[11], wz = x[12];
   o[3] = 0.5f * (-(qx * wx) - qy * wy - qz * wz);
   o[4] = 0.5f * (qw * wx + qy * wz - qz * wy);
   o[5] = 0.5f * (qw * wy - qx * wz + qz * wx);
   o[6] = 0.5f * (qw * wz + qx * wy - qy * wx);
   o[7] = s * (2.f * (qx * qz + qw * qy));
   o[8] = s * (2.f * (qy * qz - qw * qx));
-  o[9] = s * (cst(1.f) - 2.f * (qx * qx + qy * qy)) - P.g;
-  o[10] = tx - P.cx * wy * wz;
-  o[11] = ty - P.cy * wz * wx;
-  o[12] = tz - P.cz * wx * wy;
+  N one{};
+  one.v = 1.f;
+  o[9] = s * (one - 2.f * (qx * qx + qy * qy)) - lift(P.g, (N*)nullptr);
+  o[10] = tx - (wy * wz) * P.cx;
+  o[11] = ty - (wz * wx) * P.cy;
+  o[12] = tz - (wx * wy) * P.cz;
 }
 
-// one RK4 step with the thrust held; x and the result are 13 five-part numbers
-__device__ __forceinline__ void rk4_5(const PN& P, const N5* x, const N5* u, N5* xn) {
-  const N5 s = (u[0] + u[1] + u[2] + u[3]) * P.im;
-  const N5 tx = P.a * (u[0] + u[1] - u[2] - u[3]) * P.iJx;
-  const N5 ty = P.a * (u[1] + u[2] - u[0] - u[3]) * P.iJy;
-  const N5 tz = P.kappa * (u[0] - u[1] + u[2] - u[3]) * P.iJz;
-  const N5 h2 = 0.5f * P.h, h6 = (1.f / 6.f) * P.h;
-  N5 k[NX], acc[NX], xs[NX];
-  rhs5(P, x, s, tx, ty, tz, k);
+// one RK4 step with the thrust held.  Position enters no derivative, so the
+// stage points keep only q, v, w, and the position's stage derivative (the
+// stage point's velocity) is accumulated directly.
+template <class N>
+__device__ __forceinline__ void rk4_n(const PN& P, const N* x, const N* u, N* xn) {
+  const N s = (u[0] + u[1] + u[2] + u[3]) * P.im;
+  const N tx = ((u[0] + u[1] - u[2] - u[3]) * P.a) * P.iJx;
+  const N ty = ((u[1] + u[2] - u[0] - u[3]) * P.a) * P.iJy;
+  const N tz = ((u[0] - u[1] + u[2] - u[3]) * P.kappa) * P.iJz;
+  N acc[NX], xs[NX], k[NX];
 #pragma unroll
-  for (int i = 0; i < NX; ++i) {
-    acc[i] = k[i];
-    xs[i] = x[i] + h2 * k[i];
+  for (int i = 0; i < NX; ++i) xs[i] = x[i];
+  // stage 1
+  rhs_qvw(P, xs, s, tx, ty, tz, k);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) acc[i] = xs[7 + i];
+#pragma unroll
+  for (int i = 3; i < NX; ++i) acc[i] = k[i];
+#pragma unroll
+  for (int i = 3; i < NX; ++i) xs[i] = x[i] + k[i] * P.h2;
+  // stages 2 and 3 (weight 2)
+#pragma unroll
+  for (int st = 0; st < 2; ++st) {
+    rhs_qvw(P, xs, s, tx, ty, tz, k);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc[i] = acc[i] + 2.f * xs[7 + i];
+#pragma unroll
+    for (int i = 3; i < NX; ++i) acc[i] = acc[i] + 2.f * k[i];
+    const P2 c = (st == 0) ? P.h2 : P.h;
+#pragma unroll
+    for (int i = 3; i < NX; ++i) xs[i] = x[i] + k[i] * c;
   }
-  rhs5(P, xs, s, tx, ty, tz, k);
+  // stage 4
+  rhs_qvw(P, xs, s, tx, ty, tz, k);
 #pragma unroll
-  for (int i = 0; i < NX; ++i) {
-    acc[i] = acc[i] + 2.f * k[i];
-    xs[i] = x[i] + h2 * k[i];
-  }
-  rhs5(P, xs, s, tx, ty, tz, k);
+  for (int i = 0; i < 3; ++i) xn[i] = x[i] + (acc[i] + xs[7 + i]) * P.h6;
 #pragma unroll
-  for (int i = 0; i < NX; ++i) {
-    acc[i] = acc[i] + 2.f * k[i];
-    xs[i] = x[i] + P.h * k[i];
-  }
-  rhs5(P, xs, s, tx, ty, tz, k);
-#pragma unroll
-  for (int i = 0; i < NX; ++i) xn[i] = x[i] + h6 * (acc[i] + k[i]);
+  for (int i = 3; i < NX; ++i) xn[i] = x[i] + (acc[i] + k[i]) * P.h6;
 }
 
-// one stage of the recursions on lane j < 8: xi, eta <- their values at t + 1
-__device__ __forceinline__ void propagate(const PN& P, const float* xs, const float* us, const float* xt,
-                                          const float* ut, float* xi, float* eta) {
-  N5 x[NX], u[NU], y[NX];
+// lane j < 8: xi_j <- xi_j at t + 1
+__device__ __forceinline__ void propagate_xi(const PN& P, const float* xs, const float* us, float* xi) {
+  D2 x[NX], u[NU], y[NX];
 #pragma unroll
-  for (int i = 0; i < NX; ++i) x[i] = {xs[i], xt[i], 0.f, eta[i], xi[i]};
+  for (int i = 0; i < NX; ++i) x[i] = {xs[i], xi[i]};
 #pragma unroll
-  for (int a = 0; a < NU; ++a) u[a] = {us[a], ut[a], 0.f, 0.f, 0.f};
-  rk4_5(P, x, u, y);
+  for (int a = 0; a < NU; ++a) u[a] = {us[a], 0.f};
+  rk4_n(P, x, u, y);
 #pragma unroll
-  for (int i = 0; i < NX; ++i) {
-    xi[i] = y[i].s;
-    eta[i] = y[i].ed;
-  }
+  for (int i = 0; i < NX; ++i) xi[i] = y[i].s;
+}
+
+// lane 8 + j: eta_j <- eta_j at t + 1
+__device__ __forceinline__ void propagate_eta(const PN& P, const float* xs, const float* us, const float* xt,
+                                              const float* ut, float* eta) {
+  H4 x[NX], u[NU], y[NX];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) x[i] = {xs[i], xt[i], 0.f, eta[i]};
+#pragma unroll
+  for (int a = 0; a < NU; ++a) u[a] = {us[a], ut[a], 0.f, 0.f};
+  rk4_n(P, x, u, y);
+#pragma unroll
+  for (int i = 0; i < NX; ++i) eta[i] = y[i].ed;
 }
 
 }  // namespace dmpc_theta
