@@ -79,7 +79,7 @@ extern "C" {
                                by stage; instances whose check fails take the serial sweep.  Same
                                results as the serial form up to rounding; meant for small B and long
                                T, where the serial recursion in time sets the latency.  Sizes the
-                               workspace for it (16 KiB more per instance-stage) */
+                               workspace for it (about 8.4 KiB more per instance-stage) */
 
 /* per-instance status word */
 #define DMPC_ST_CONVERGED 0x1u   /* tol_du > 0 and ||U^k - U^{k-1}||_inf < tol_du was reached */

@@ -118,3 +118,16 @@ def test_tuned_workspace_holds_the_per_launch_buffer(D):
     tuned = D.workspace_bytes(D.make_config(256, 20, flags=D.NEED_GRAD | D.TUNED))
     pers = D.workspace_bytes(D.make_config(256, 20, flags=D.NEED_GRAD))
     assert tuned == plain and tuned - pers >= 256 * 20 * 272 * 4
+
+
+def test_time_parallel_workspace(D):
+    """DMPC_TPAR adds the linearisation buffer, two element buffers of 536
+    doubles per instance-stage and one pattern byte per instance-stage."""
+    base = D.workspace_bytes(D.make_config(64, 30))
+    plain = D.workspace_bytes(D.make_config(64, 30, flags=D.PLAIN))
+    tpar = D.workspace_bytes(D.make_config(64, 30, flags=D.TPAR))
+    extra = tpar - plain
+    assert plain > base
+    assert 2 * 64 * 30 * 536 * 8 + 64 * 30 <= extra <= 2 * 64 * 30 * 536 * 8 + 64 * 30 + 2 * 256
+    assert D.validate(D.make_config(4, 10, flags=D.TPAR | D.NEED_GRAD)) == 0
+    assert D.validate(D.make_config(4, 10, flags=0x20)) == -1
