@@ -22,7 +22,7 @@ def _check(d, g, idx=None):
     return err, o
 
 
-@pytest.mark.parametrize("case", ["cfg0", "cfg0_free", "ragged", "dense", "ckpt", "plain"])
+@pytest.mark.parametrize("case", ["cfg0", "cfg0_free", "ragged", "dense", "ckpt", "plain", "tpar"])
 def test_theta_gradient_matches_oracle(case):
     if case == "cfg0":
         d, kw = W.make(0), {}
@@ -35,8 +35,10 @@ def test_theta_gradient_matches_oracle(case):
         d, kw = W.make(4, B=64, T=12, seed=2103), {}
     elif case == "ckpt":
         d, kw = W.make(0, B=64, T=14, pu_scale=0.01, seed=2104), dict(ckpt=4)
-    else:
+    elif case == "plain":
         d, kw = W.make(0, B=64, T=12, pu_scale=0.01, seed=2105), dict(plain=True)
+    else:  # stage factors from the time-parallel tail
+        d, kw = W.make(0, B=16, T=20, pu_scale=0.01, seed=2108), dict(tpar=True)
     g = run_gpu(d, theta=True, **kw)
     err, o = _check(d, g)
     assert np.all(np.isfinite(g["gdyn"]))
