@@ -941,6 +941,14 @@ __device__ __forceinline__ double* elem_at(const KArgs& A, int buf, int b, int t
   return A.ws.elem + (((size_t)buf * A.B + b) * A.Tm + t) * EL_W;
 }
 
+// value of v in lane `lane` (a wave-uniform index) of the wavefront
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // out = op(X) op(Y) for 13 x 13 row-major matrices in LDS (tX / tY
 // transpose), outputs spread over the NT threads of the block
 template <int NT>
@@ -1143,7 +1151,7 @@ __global__ __launch_bounds__(64) void k_tpar_elem(KArgs A, int tail) {
 template <int NT>
 __global__ __launch_bounds__(NT) void k_tpar_scan(KArgs A, int step, int src, int tail) {
   __shared__ double Ai[169], Ci[169], Ji[169], Aj[169], Cj[169], Jj[169], bi[13], ei[13], bj[13], ej[13];
-  __shared__ double G0[13 * 26], G1[13 * 26], X1[169], X2[169], X3[169], v1[13], v2[13];
+  __shared__ double X1[169], X2[169], X3[169], v1[13], v2[13];
   const int tid = threadIdx.x;
   const int unit = blockIdx.x, b = unit / A.Tm, t = unit % A.Tm;
   const int* s = A.ws.state + (size_t)b * SW;
@@ -1173,43 +1181,53 @@ __global__ __launch_bounds__(NT) void k_tpar_scan(KArgs A, int step, int src, in
     }
   }
   __syncthreads();
-  // [M | I] with M = I + C_i J_j
+  // M = I + C_i J_j (X1 holds C_i J_j)
   lds_mm<NT>(X1, Ci, Jj, false, false);
-  for (int idx = tid; idx < 13 * 26; idx += NT) {
-    const int r = idx / 26, c = idx % 26;
-    G0[idx] = (c < 13) ? X1[r * 13 + c] + (r == c ? 1.0 : 0.0) : ((c - 13) == r ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  // Gauss-Jordan with partial pivoting, ping-pong between G0 and G1: the
-  // pivot row (old row p, scaled) goes to row k, old row k to row p.  Every
-  // thread finds the pivot itself from column k (broadcast LDS reads), so a
-  // step needs one barrier.
-  double* S = G0;
-  double* D = G1;
-  for (int k = 0; k < 13; ++k) {
-    int p = k;
-    double best = fabs(S[k * 26 + k]);
+  // X2 = M^-1 by Gauss-Jordan on [M | I] in the registers of the first wave,
+  // one row per lane (lanes 0..12), with implicit partial pivoting: the pivot
+  // row of step k stays in its lane and reaches the others by readlane, and
+  // no rows move; at the end the lane that was pivot at step k holds row k of
+  // M^-1.  No barrier inside the elimination.
+  if (tid < 64) {
+    const int r = tid;
+    double a[26];
 #pragma unroll
-    for (int r = 1; r < 13; ++r) {
-      const double a = fabs(S[r * 26 + k]);
-      const bool take = (r > k) && (a > best);
-      best = take ? a : best;
-      p = take ? r : p;
+    for (int c = 0; c < 26; ++c) {
+      double v = 0.0;
+      if (r < 13) v = (c < 13) ? X1[r * 13 + c] + (r == c ? 1.0 : 0.0) : ((c - 13) == r ? 1.0 : 0.0);
+      a[c] = v;
     }
-    const double ip = rcp_nr(S[p * 26 + k]);
-    for (int idx = tid; idx < 13 * 26; idx += NT) {
-      const int r = idx / 26, c = idx % 26;
-      const double pr = S[p * 26 + c] * ip;
-      const int rr = (r == p) ? k : r;
-      D[idx] = (r == k) ? pr : fma(-S[rr * 26 + k], pr, S[rr * 26 + c]);
+    bool used = (r >= 13);
+    int mystep = 0;
+#pragma unroll
+    for (int k = 0; k < 13; ++k) {
+      const double cand = used ? -1.0 : fabs(a[k]);
+      int p = 0;
+      double best = -2.0;
+#pragma unroll
+      for (int q = 0; q < 13; ++q) {
+        const double vq = readlane_f64(cand, q);
+        const bool take = vq > best;
+        best = take ? vq : best;
+        p = take ? q : p;
+      }
+      p = __builtin_amdgcn_readfirstlane(p);
+      double pr[26];
+#pragma unroll
+      for (int c = 0; c < 26; ++c) pr[c] = readlane_f64(a[c], p);
+      const double ip = rcp_nr(pr[k]);
+      const double f = a[k] * ip;
+      const bool piv = (r == p);
+#pragma unroll
+      for (int c = 0; c < 26; ++c) a[c] = piv ? pr[c] * ip : fma(-f, pr[c], a[c]);
+      mystep = piv ? k : mystep;
+      used = used || piv;
     }
-    __syncthreads();
-    double* tmp = S;
-    S = D;
-    D = tmp;
+    if (r < 13) {
+#pragma unroll
+      for (int c = 0; c < 13; ++c) X2[mystep * 13 + c] = a[13 + c];
+    }
   }
-  // X2 = M^-1
-  for (int k = tid; k < 169; k += NT) X2[k] = S[(k / 13) * 26 + 13 + k % 13];
   __syncthreads();
   // b = A_j M^-1 (b_i + C_i eta_j) + b_j
   lds_mv(v1, Ci, ej, false);
