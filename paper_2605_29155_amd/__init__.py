@@ -238,32 +238,40 @@ def _make_function():
     import torch
 
     class DMPCFunction(torch.autograd.Function):
-        """u*, x*, status = DMPCFunction.apply(x0, Q, p, u_lo, u_hi, T, layer).
+        """u*, x*, status = DMPCFunction.apply(x0, Q, p, u_lo, u_hi, T, dyn, layer).
 
-        Differentiable in x0, Q and p (Sec. IV after eq. (3)); the backward
-        reuses the stage factors the forward stored in its workspace."""
+        Differentiable in x0, Q and p (Sec. IV after eq. (3)) and, when dyn
+        (the eight model constants as a tensor) is given, in dyn: its gradient
+        is the batch sum of the per-instance dL/dtheta.  The backward reuses
+        the stage factors the forward stored in its workspace."""
 
         @staticmethod
-        def forward(ctx, x0, Q, p, u_lo, u_hi, T, layer):
+        def forward(ctx, x0, Q, p, u_lo, u_hi, T, dyn, layer):
             # the C ABI reads dense row-major float32 buffers
             x0, Q, p, u_lo, u_hi = (a.detach().float().contiguous() for a in (x0, Q, p, u_lo, u_hi))
             if T is not None:
                 T = T.to(torch.int32).contiguous()
+            # the constants are passed by value: a tensor on the GPU costs one synchronisation here
+            params = layer.params if dyn is None else QuadParams(*dyn.detach().double().cpu().reshape(8).tolist())
             B, Tm = p.shape[0], p.shape[1]
-            need = any(ctx.needs_input_grad[:3])
+            want_dyn = dyn is not None and ctx.needs_input_grad[6]
+            need = any(ctx.needs_input_grad[:3]) or want_dyn
             cfg = layer.config(B, Tm, need_grad=need)
             ws = alloc_workspace(cfg, p.device)
             u = torch.empty(B, Tm, NU, device=p.device, dtype=torch.float32)
             x = torch.empty(B, Tm, NX, device=p.device, dtype=torch.float32)
             st = torch.empty(B, device=p.device, dtype=torch.int32)
             if layer.autotune and get_tuned(layer.handle, cfg, T is not None) is None:
-                autotune(layer.handle, cfg, layer.params, x0, Q, p, u_lo, u_hi, T, u, x, st, ws)
+                autotune(layer.handle, cfg, params, x0, Q, p, u_lo, u_hi, T, u, x, st, ws)
             else:
-                forward_raw(layer.handle, cfg, layer.params, x0, Q, p, u_lo, u_hi, T, u, x, st, ws)
-            ctx.cfg, ctx.ws, ctx.layer = cfg, ws, layer
-            # the checkpointed backward recomputes stage factors from the inputs
-            ctx.inputs = (Q, p, u_lo, u_hi) if cfg.ckpt_every > 0 else (None,) * 4
+                forward_raw(layer.handle, cfg, params, x0, Q, p, u_lo, u_hi, T, u, x, st, ws)
+            ctx.cfg, ctx.ws, ctx.layer, ctx.params = cfg, ws, layer, params
+            # the checkpointed backward recomputes stage factors from the inputs,
+            # and dL/dtheta reads the cost
+            ctx.inputs = (Q, p, u_lo, u_hi) if (cfg.ckpt_every > 0 or want_dyn) else (None,) * 4
             ctx.shapes = (x0.shape, Q.shape, p.shape)
+            ctx.want_dyn = want_dyn
+            ctx.dyn_meta = None if dyn is None else (dyn.shape, dyn.dtype, dyn.device)
             ctx.mark_non_differentiable(st)
             return u, x, st
 
@@ -276,8 +284,14 @@ def _make_function():
             gQ = torch.empty(sQ, device=dev, dtype=torch.float32)
             gp = torch.empty(sp, device=dev, dtype=torch.float32)
             gx0 = torch.empty(sx0, device=dev, dtype=torch.float32)
-            backward_raw(ctx.layer.handle, ctx.cfg, ctx.layer.params, *ctx.inputs, ctx.ws, gu, gx, gQ, gp, gx0)
-            return gx0, gQ, gp, None, None, None, None
+            gd = torch.empty(sp[0], 8, device=dev, dtype=torch.float32) if ctx.want_dyn else None
+            backward_raw(ctx.layer.handle, ctx.cfg, ctx.params, *ctx.inputs, ctx.ws, gu, gx, gQ, gp, gx0,
+                         grad_dyn=gd)
+            gdyn = None
+            if gd is not None:
+                shape, dtype, ddev = ctx.dyn_meta
+                gdyn = gd.double().sum(0).to(device=ddev, dtype=dtype).reshape(shape)
+            return gx0, gQ, gp, None, None, None, gdyn, None
 
     return DMPCFunction
 
@@ -294,7 +308,11 @@ def DMPCFunction():
 
 
 class DMPCLayer:
-    """Callable layer: (x0, Q, p, u_lo, u_hi, T=None) -> (u*, x*, status)."""
+    """Callable layer: (x0, Q, p, u_lo, u_hi, T=None, dyn=None) -> (u*, x*, status).
+
+    dyn: optional tensor of the eight model constants (mass, Jxx, Jyy, Jzz,
+    arm, kappa, dt, g) used instead of the layer's; when it requires grad,
+    the backward returns dL/d(dyn) (the batch sum of dL/dtheta)."""
 
     def __init__(self, params, max_iter=5, tol_du=0.0, cost_kind=COST_DIAG, plain=False, lpt=True,
                  fp64_pivot=1e-6, ckpt_every=0, autotune=False, tpar=False, device=0):
@@ -315,5 +333,5 @@ class DMPCLayer:
         return make_config(B, T_max, self.cost_kind, self.max_iter, self.tol_du, flags, self.fp64_pivot,
                            self.ckpt_every)
 
-    def __call__(self, x0, Q, p, u_lo, u_hi, T=None):
-        return DMPCFunction().apply(x0, Q, p, u_lo, u_hi, T, self)
+    def __call__(self, x0, Q, p, u_lo, u_hi, T=None, dyn=None):
+        return DMPCFunction().apply(x0, Q, p, u_lo, u_hi, T, dyn, self)

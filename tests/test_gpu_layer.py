@@ -56,6 +56,41 @@ def test_autograd_function_matches_raw_backward_and_oracle():
     assert all(prm.grad is not None and torch.isfinite(prm.grad).all() for prm in mlp.params)
 
 
+def test_autograd_gradient_of_the_model_constants():
+    """dyn as a layer input: the forward uses its values, and its gradient is
+    the batch sum of the per-instance dL/dtheta of the raw C ABI (which the
+    oracle tests pin); a perturbed mass gives the raw API's solution for that
+    mass."""
+    import torch
+
+    import paper_2605_29155_amd as D
+    d = W.make(0, B=32, T=12, pu_scale=0.01, seed=2201)
+    dev = "cuda:0"
+    qp = dict(W.quad_params_f32(), mass=0.8)
+    dyn = torch.tensor([qp[n] for n in orc.THETA_NAMES], dtype=torch.float32, requires_grad=True)
+    layer = D.DMPCLayer(W.quad_params_f32(), max_iter=d["K"])
+    t = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev) for k in ("x0", "Q", "p", "lo", "hi", "grad_u")}
+    u, x, st = layer(t["x0"], t["Q"], t["p"], t["lo"], t["hi"], dyn=dyn)
+    (u * t["grad_u"]).sum().backward()
+    torch.cuda.synchronize()
+    # the raw path with the same constants
+    h = handle()
+    cfg = D.make_config(32, 12, 0, d["K"], 0.0, D.NEED_GRAD | D.LPT)
+    par = D.quad_params(qp)
+    ws = D.alloc_workspace(cfg, dev)
+    ur, xr = torch.empty_like(u), torch.empty_like(x)
+    sr = torch.empty_like(st)
+    D.forward_raw(h, cfg, par, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], None, ur, xr, sr, ws)
+    gQ, gp, gx0 = torch.empty_like(t["Q"]), torch.empty_like(t["p"]), torch.empty_like(t["x0"])
+    gd = torch.empty(32, 8, device=dev)
+    D.backward_raw(h, cfg, par, t["Q"], t["p"], t["lo"], t["hi"], ws, t["grad_u"], None, gQ, gp, gx0, grad_dyn=gd)
+    torch.cuda.synchronize()
+    assert torch.equal(u, ur)
+    ref = gd.double().sum(0).cpu().numpy()
+    assert dyn.grad is not None and dyn.grad.shape == (8,)
+    assert np.abs(dyn.grad.numpy() - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
 def test_graph_replay_equals_direct_launch():
     import torch
 
