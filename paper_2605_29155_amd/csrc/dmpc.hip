@@ -378,7 +378,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     // stage cost: Q += C_t, q = g + F^T v with g = C_t z + c_t
     const size_t srow = (size_t)b * A.Tm + t;
     const float* prow = A.p + srow * NZ;
-    double qc, g0, c00;
+    double qc, g0, c00, qdiag = 0.0;
     {
       const double zb_c = (double)s_zc;
       if (!DENSE) {
@@ -386,8 +386,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
         c00 = (double)s_q0;
         qc = fma(qd_c, zb_c, (double)s_pc);
         g0 = fma(c00, (double)zb[0], (double)s_p0);
-#pragma unroll
-        for (int i = 1; i < NZ; ++i) Qc[i] += (i == col) ? qd_c : 0.0;
+        qdiag = qd_c;
       } else {
         const float* crow = A.Q + srow * NPK;
         double gc = (double)prow[col], gz = (double)prow[0];
@@ -411,6 +410,15 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     {
       double h[10];
       hq_block(h, qu, Qc, qc);
+      // a diagonal cost adds to the diagonal only: its four control entries
+      // here, the state entry of the parked column below (rather than a
+      // 16-way select over this lane's column)
+      if (!DENSE) {
+        h[0] += bc<13>(qdiag);
+        h[2] += bc<14>(qdiag);
+        h[5] += bc<15>(qdiag);
+        h[9] += bc<0>(qdiag);
+      }
       int m = 0;
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb)
@@ -421,6 +429,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
         }
     }
     lds_write<NX>(L + L_QX + l * 14, Qc);
+    if (!DENSE && l >= 1 && l < NX) L[L_QX + l * 15] += qdiag;
     double y0b[16];  // Y[0, :] by lane (row 0 of Q without the cost)
     bcast16(y0b, Yc[0]);
     // row 0 of Q (lane 0's x-row; its own column is 16)
