@@ -130,13 +130,13 @@ def test_warm_started_forward_matches_oracle(plain):
             assert rel(xn, ro["x"]).max() <= 10 * U_BAR
 
 
-def _closed_loop(D, d, steps, K, tol, warm, plain=False, check=None):
+def _closed_loop(D, d, steps, K, tol, warm, form="persistent", check=None):
     import torch
 
     from paper_2605_29155_amd.receding import RecedingHorizon
     B, Tm = d["B"], d["T_max"]
-    rh = RecedingHorizon(W.quad_params_f32(), B, Tm, max_iter=K, tol_du=tol, warm=warm, plain=plain,
-                         handle=handle())
+    rh = RecedingHorizon(W.quad_params_f32(), B, Tm, max_iter=K, tol_du=tol, warm=warm, plain=form == "plain",
+                         tpar=form == "tpar", handle=handle())
     t = {k: _dev(d[k]) for k in ("x0", "Q", "p", "lo", "hi")}
     rh.reset(t["x0"])
     dl = torch.zeros(B, K, 1 + Tm, dtype=torch.uint8, device="cuda:0")
@@ -154,8 +154,8 @@ def _closed_loop(D, d, steps, K, tol, warm, plain=False, check=None):
     return np.array(xs), np.array(sts)
 
 
-@pytest.mark.parametrize("plain", [False, True])
-def test_closed_loop_driver_matches_oracle_step_by_step(plain):
+@pytest.mark.parametrize("form", ["persistent", "plain", "tpar"])
+def test_closed_loop_driver_matches_oracle_step_by_step(form):
     """Every control step of the device loop against the oracle from the same
     state and warm start (decisions replayed), and the state it reaches
     against the oracle's RK4 step under the applied control."""
@@ -173,7 +173,7 @@ def test_closed_loop_driver_matches_oracle_step_by_step(plain):
         step = np.stack([orc.rk4(P, xb[b].astype(np.float64), ua[b].astype(np.float64)) for b in range(B)])
         worst["x"] = max(worst["x"], rel(xa, step).max())
 
-    _closed_loop(D, d, 6, K, tol, True, plain, check)
+    _closed_loop(D, d, 6, K, tol, True, form, check)
     assert worst["u"] <= U_BAR, worst
     assert worst["x"] <= X_BAR, worst
 
