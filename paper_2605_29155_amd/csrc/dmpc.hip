@@ -314,12 +314,21 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     const float s_q0 = DENSE ? 0.f : A.Q[srow0 * NZ];
     const float s_pc = A.p[srow0 * NZ + col];
     const float s_p0 = A.p[srow0 * NZ];
+    // No branch around these loads (nor around the stores at the end of the
+    // stage): the wait-count insertion assumes the fewest operations in flight
+    // over the paths into a wait, so a skippable load or store makes a later
+    // wait also cover the loads issued after it.  The previous iteration's k
+    // (the box-QP's warm start) is read at every iteration and ignored at the
+    // first; at the last stage the "next" nominal is this stage's again.
     float4 s_kw = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (MODE == 0 && kit > 0) s_kw = *(const float4*)(gains_at(A, b, t) + 64);
+    if (MODE == 0) {
+      const float4 w = *(const float4*)(gains_at(A, b, t) + 64);
+      if (kit > 0) s_kw = w;
+    }
     float zb[NZ];
 #pragma unroll
     for (int i = 0; i < NZ; ++i) zb[i] = zn[i];
-    if (t > t_lo) load_z(traj_at(A, b, n, t - 1), zn);
+    load_z(traj_at(A, b, n, t > t_lo ? t - 1 : t), zn);
     const bool has_dyn = (t + 1 < T);
     float Fc[NX];
     if (has_dyn) {
@@ -430,8 +439,9 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     }
     lds_write<NX>(L + L_QX + l * 14, Qc);
     if (!DENSE && l >= 1 && l < NX) L[L_QX + l * 15] += qdiag;
-    double y0b[16];  // Y[0, :] by lane (row 0 of Q without the cost)
-    bcast16(y0b, Yc[0]);
+    // Y[0, :] by lane (row 0 of Q without the cost), broadcast only after the
+    // box-QP so that its 32 registers are free during the QP
+    double y0b[16];
     // row 0 of Q (lane 0's x-row; its own column is 16)
     auto R0 = [&](int j) -> double {
       double r = (j == 0) ? v00 + c00 : y0b[lane_of(j)];
@@ -458,6 +468,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
       chol4(H, fr, A.piv, C, st);
     }
 
+    bcast16(y0b, Yc[0]);
     // gain column: K[:, l] = -Qff^{-1} Q_ux[:, l] on the free rows, 0 on clamped rows
     double Qux[4], Kd[4];
 #pragma unroll
@@ -504,11 +515,12 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     if (l < NX) lds_read<NX>(L + L_V + l * 14, Vr);
 
     if (MODE == 0) {
-      if (l < NX) {
+      // no branch around the stores (see the loads at the top of the stage):
+      // lanes 13..15 fill the unused padding of the gain rows, and every lane
+      // writes the same k
 #pragma unroll
-        for (int a = 0; a < 4; ++a) gp[a * 16 + l] = Kc[a];
-      }
-      if (l == NX) *(float4*)(gp + 64) = make_float4((float)kv[0], (float)kv[1], (float)kv[2], (float)kv[3]);
+      for (int a = 0; a < 4; ++a) gp[a * 16 + l] = Kc[a];
+      *(float4*)(gp + 64) = make_float4((float)kv[0], (float)kv[1], (float)kv[2], (float)kv[3]);
       if ((A.dlog || A.ws.pat) && l == 0) {
         unsigned code = 0;
 #pragma unroll
@@ -585,6 +597,50 @@ __device__ __forceinline__ void ls_load(const KArgs& A, int b, int n, int t, int
   }
 }
 
+// one stage of the line search: control, cost and stage record from cur and
+// the state x, prefetch of the next stage into nxt, the next state into xn
+template <bool DENSE>
+__device__ __forceinline__ void ls_stage(const KArgs& A, int b, int n, int t, int T, int r, int sc, float alpha,
+                                         float lo_r, float hi_r, const LsStage<DENSE>& cur, LsStage<DENSE>& nxt,
+                                         const float* x, float* xn, float& J, float& dm) {
+  if (t + 1 < T) ls_load<DENSE>(A, b, n, t + 1, r, nxt);
+  float ur = cur.ub + alpha * cur.kr;
+#pragma unroll
+  for (int j = 0; j < NX; ++j) ur = fmaf(cur.Kr[j], x[j] - cur.xb[j], ur);
+  ur = clampf(ur, lo_r, hi_r);
+  dm = fmaxf(dm, fabsf(ur - cur.ub));
+  float z[NZ];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) z[i] = x[i];
+#pragma unroll
+  for (int c = 0; c < NU; ++c) z[NX + c] = qb(ur, c);
+  const size_t srow = (size_t)b * A.Tm + t;
+  if (!DENSE) {
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) J = fmaf(fmaf(0.5f * cur.q[i], z[i], cur.p[i]), z[i], J);
+  } else {
+    const float* crow = A.Q + srow * NPK;
+    int m = 0;
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) {
+      float s = 0.5f * crow[m++] * z[i];
+#pragma unroll
+      for (int j = i + 1; j < NZ; ++j) s = fmaf(crow[m++], z[j], s);
+      J = fmaf(s + cur.p[i], z[i], J);
+    }
+  }
+  {
+    // lane r of the quad writes floats 4r..4r+3 of the stage record, lane 0 also the controls
+    float* zo = traj_at(A, b, sc, t);
+    const float4 w = r == 0 ? make_float4(x[0], x[1], x[2], x[3])
+                   : (r == 1 ? make_float4(x[4], x[5], x[6], x[7])
+                   : (r == 2 ? make_float4(x[8], x[9], x[10], x[11]) : make_float4(x[12], 0.f, 0.f, 0.f)));
+    *(float4*)(zo + 4 * r) = w;
+    if (r == 0) *(float4*)(zo + 16) = make_float4(z[13], z[14], z[15], z[16]);
+  }
+  if (t + 1 < T) rk4(A.P, x, z + NX, xn);
+}
+
 template <bool DENSE>
 __device__ void grp_ls(const KArgs& A, const Grp& G, int n, float& Jout, float& dmax) {
   const int a = G.l >> 2, r = G.l & 3, b = G.b, T = G.T;
@@ -595,55 +651,19 @@ __device__ void grp_ls(const KArgs& A, const Grp& G, int n, float& Jout, float& 
 #pragma unroll
   for (int i = 0; i < NX; ++i) x[i] = A.x0[(size_t)b * NX + i];
   float J = 0.f, dm = 0.f;
-  LsStage<DENSE> cur, nxt;
-  if (T > 0) ls_load<DENSE>(A, b, n, 0, r, cur);
+  LsStage<DENSE> sa, sb;
+  if (T > 0) ls_load<DENSE>(A, b, n, 0, r, sa);
   // Let the first stage's loads land before the loop: with loads still
   // pending on entry, the wait counters inside the loop have to assume that
   // any register could be one of them, and (the vector-memory counter being
   // in order) the loop would wait on the next stage's prefetch at every stage.
   __builtin_amdgcn_s_waitcnt(0);
-  for (int t = 0; t < T; ++t) {
-    if (t + 1 < T) ls_load<DENSE>(A, b, n, t + 1, r, nxt);
-    float ur = cur.ub + alpha * cur.kr;
-#pragma unroll
-    for (int j = 0; j < NX; ++j) ur = fmaf(cur.Kr[j], x[j] - cur.xb[j], ur);
-    ur = clampf(ur, lo_r, hi_r);
-    dm = fmaxf(dm, fabsf(ur - cur.ub));
-    float z[NZ];
-#pragma unroll
-    for (int i = 0; i < NX; ++i) z[i] = x[i];
-#pragma unroll
-    for (int c = 0; c < NU; ++c) z[NX + c] = qb(ur, c);
-    const size_t srow = (size_t)b * A.Tm + t;
-    if (!DENSE) {
-#pragma unroll
-      for (int i = 0; i < NZ; ++i) J = fmaf(fmaf(0.5f * cur.q[i], z[i], cur.p[i]), z[i], J);
-    } else {
-      const float* crow = A.Q + srow * NPK;
-      int m = 0;
-#pragma unroll
-      for (int i = 0; i < NZ; ++i) {
-        float s = 0.5f * crow[m++] * z[i];
-#pragma unroll
-        for (int j = i + 1; j < NZ; ++j) s = fmaf(crow[m++], z[j], s);
-        J = fmaf(s + cur.p[i], z[i], J);
-      }
-    }
-    {
-      // lane r of the quad writes floats 4r..4r+3 of the stage record, lane 0 also the controls
-      float* zo = traj_at(A, b, sc, t);
-      const float4 w = r == 0 ? make_float4(x[0], x[1], x[2], x[3])
-                     : (r == 1 ? make_float4(x[4], x[5], x[6], x[7])
-                     : (r == 2 ? make_float4(x[8], x[9], x[10], x[11]) : make_float4(x[12], 0.f, 0.f, 0.f)));
-      *(float4*)(zo + 4 * r) = w;
-      if (r == 0) *(float4*)(zo + 16) = make_float4(z[13], z[14], z[15], z[16]);
-    }
-    if (t + 1 < T) {
-      rk4(A.P, x, z + NX, xn);
-#pragma unroll
-      for (int i = 0; i < NX; ++i) x[i] = xn[i];
-      cur = nxt;
-    }
+  // two stages per trip with the stage records and the state swapping roles,
+  // so that nothing is copied from one stage to the next
+  for (int t = 0; t < T; t += 2) {
+    ls_stage<DENSE>(A, b, n, t, T, r, sc, alpha, lo_r, hi_r, sa, sb, x, xn, J, dm);
+    if (t + 1 >= T) break;
+    ls_stage<DENSE>(A, b, n, t + 1, T, r, sc, alpha, lo_r, hi_r, sb, sa, xn, x, J, dm);
   }
   Jout = J;  // all four lanes of a quad hold the same cost
   dmax = quad_max(dm);
