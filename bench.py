@@ -40,10 +40,13 @@ def flops_per_solve(T, K, dense=False):
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources and the compiler flags they are built with."""
+    from paper_2605_29155_amd import build as _b
     h = hashlib.sha256()
     for f in ("paper_2605_29155_amd/csrc/dmpc.hip", "paper_2605_29155_amd/csrc/dmpc_device.hpp",
               "paper_2605_29155_amd/csrc/dmpc_theta.hpp", "include/dmpc.h"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
+    h.update(" ".join(f for f in _b.FLAGS if not f.startswith("-I")).encode())
     return h.hexdigest()[:16]
 
 

@@ -14,6 +14,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 VALU ops stay disabled: they are not used by this library
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # a multiply and an add are fused only where one expression holds both
+         # (or fmaf says so), never across statements: the arithmetic then does
+         # not depend on how the code is split into blocks
+         "-ffp-contract=on",
          "-I" + os.path.join(ROOT, "include")]
 
 

@@ -603,7 +603,9 @@ template <bool DENSE>
 __device__ __forceinline__ void ls_stage(const KArgs& A, int b, int n, int t, int T, int r, int sc, float alpha,
                                          float lo_r, float hi_r, const LsStage<DENSE>& cur, LsStage<DENSE>& nxt,
                                          const float* x, float* xn, float& J, float& dm) {
-  if (t + 1 < T) ls_load<DENSE>(A, b, n, t + 1, r, nxt);
+  // the next stage's record (at the last stage this one's again: no branch
+  // around the loads, which keeps the wait counts exact)
+  ls_load<DENSE>(A, b, n, t + 1 < T ? t + 1 : t, r, nxt);
   float ur = cur.ub + alpha * cur.kr;
 #pragma unroll
   for (int j = 0; j < NX; ++j) ur = fmaf(cur.Kr[j], x[j] - cur.xb[j], ur);
