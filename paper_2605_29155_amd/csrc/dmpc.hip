@@ -1529,8 +1529,14 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
   auto vload = [&](int t, int a0, VStage& S) {
     const float* tp = tail_at(A, b, CKPT ? t - a0 : t);
     const size_t srow = (size_t)b * Tm + t;
-    S.dc = (col < NX) ? (A.gx ? A.gx[srow * NX + col] : 0.f) : A.gu[srow * NU + (col - NX)];
-    S.d0 = A.gx ? A.gx[srow * NX] : 0.f;
+    // one load per value from a selected address (dL/du* stands in for an
+    // absent dL/dx*), so that no branch surrounds the loads
+    const float* gur = A.gu + srow * NU;
+    const float* gxr = A.gx ? A.gx + srow * NX : gur;
+    const float vdc = *((col < NX) ? gxr + (A.gx ? col : 0) : gur + (col - NX));
+    const float vd0 = *gxr;
+    S.dc = (col < NX && !A.gx) ? 0.f : vdc;
+    S.d0 = A.gx ? vd0 : 0.f;
     const float* fc = tp + col * 16;
     const float4 f0 = *(const float4*)(fc), f1 = *(const float4*)(fc + 4), f2 = *(const float4*)(fc + 8);
     S.fc[0] = f0.x; S.fc[1] = f0.y; S.fc[2] = f0.z; S.fc[3] = f0.w;
@@ -1547,40 +1553,48 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
     S.kc = *(const float4*)(tp + FS + (l < NX ? l : 0) * 4);
   };
   double vi = 0.0;
-  VStage cs, ns;
+  // one stage of the sweep from cs, the next stage's factors loaded into ns
+  auto vstep = [&](int t, int a, const VStage& cs, VStage& ns) {
+    vload(t > a ? t - 1 : t, a, ns);  // at the segment's first stage, this one's again
+    const size_t srow = (size_t)b * Tm + t;
+    double Fd[NX];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) Fd[k] = (double)cs.fc[k];
+    double qc = (double)cs.dc;
+    fv_chain(qc, vi, Fd);
+    const double q0 = (double)cs.d0 + bc<0>(vi);
+    double qu[4];
+#pragma unroll
+    for (int a4 = 0; a4 < 4; ++a4) qu[a4] = rb64(qc, lane_of(NX + a4));
+    double kt[4];
+#pragma unroll
+    for (int a4 = 0; a4 < 4; ++a4) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc = fma(cs.M[a4 * 4 + c], qu[c], acc);
+      kt[a4] = -acc;
+    }
+    // every lane of the instance writes the same k~ (no branch around the store)
+    *(float4*)(A.ws.ktil + srow * 4) = make_float4((float)kt[0], (float)kt[1], (float)kt[2], (float)kt[3]);
+    double vn = (l == 0) ? q0 : qc;
+    vn = fma((double)cs.kc.x, qu[0], vn);
+    vn = fma((double)cs.kc.y, qu[1], vn);
+    vn = fma((double)cs.kc.z, qu[2], vn);
+    vn = fma((double)cs.kc.w, qu[3], vn);
+    vi = (l < NX) ? vn : 0.0;
+  };
+  VStage s0, s1;
   for (int sg = nseg - 1; sg >= 0; --sg) {
     const int a = sg * seg, e = (a + seg < T) ? a + seg : T;
     if (CKPT) recompute(a, e);
-    vload(e - 1, a, cs);
+    vload(e - 1, a, s0);
     __builtin_amdgcn_s_waitcnt(0);  // no load pending on loop entry (see grp_ls)
-    for (int t = e - 1; t >= a; --t) {
-      if (t > a) vload(t - 1, a, ns);
-      const size_t srow = (size_t)b * Tm + t;
-      double Fd[NX];
-#pragma unroll
-      for (int k = 0; k < NX; ++k) Fd[k] = (double)cs.fc[k];
-      double qc = (double)cs.dc;
-      fv_chain(qc, vi, Fd);
-      const double q0 = (double)cs.d0 + bc<0>(vi);
-      double qu[4];
-#pragma unroll
-      for (int a4 = 0; a4 < 4; ++a4) qu[a4] = rb64(qc, lane_of(NX + a4));
-      double kt[4];
-#pragma unroll
-      for (int a4 = 0; a4 < 4; ++a4) {
-        double acc = 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc = fma(cs.M[a4 * 4 + c], qu[c], acc);
-        kt[a4] = -acc;
-      }
-      if (l == 0) *(float4*)(A.ws.ktil + srow * 4) = make_float4((float)kt[0], (float)kt[1], (float)kt[2], (float)kt[3]);
-      double vn = (l == 0) ? q0 : qc;
-      vn = fma((double)cs.kc.x, qu[0], vn);
-      vn = fma((double)cs.kc.y, qu[1], vn);
-      vn = fma((double)cs.kc.z, qu[2], vn);
-      vn = fma((double)cs.kc.w, qu[3], vn);
-      vi = (l < NX) ? vn : 0.0;
-      if (t > a) cs = ns;
+    // two stages per trip with the stage records swapping roles, so that
+    // nothing is copied from one stage to the next
+    for (int t = e - 1; t >= a; t -= 2) {
+      vstep(t, a, s0, s1);
+      if (t - 1 < a) break;
+      vstep(t - 1, a, s1, s0);
     }
   }
   if (l < NX) A.gx0[(size_t)b * NX + l] = (T > 0) ? (float)vi : 0.f;
@@ -1617,7 +1631,8 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
         S.crow[0] = A.Q[srow * NZ + r];
       }
       S.cl = A.p[srow * NZ + r];
-      S.gl = A.gx ? A.gx[srow * NX + r] : 0.f;
+      const float g = *(A.gx ? A.gx + srow * NX + r : A.p + srow * NZ + r);
+      S.gl = A.gx ? g : 0.f;
     }
   };
   float xt[NX];
@@ -1633,96 +1648,105 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
     for (int i = 0; i < NX; ++i) sv[i] = 0.f;
     PN = dmpc_theta::make_pn(A.raw, l & 7);
   }
-  FStage cf, nf;
+  // one stage of the sweep from cf, the next stage's factors loaded into nf
+  auto fstep = [&](int t, int a, int e, const FStage& cf, FStage& nf) {
+    fload(t + 1 < e ? t + 1 : t, a, nf);  // at the segment's last stage, this one's again
+    const size_t srow = (size_t)b * Tm + t;
+    float ut[4] = {cf.kk.x, cf.kk.y, cf.kk.z, cf.kk.w};
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      ut[0] = fmaf(cf.K[j].x, xt[j], ut[0]);
+      ut[1] = fmaf(cf.K[j].y, xt[j], ut[1]);
+      ut[2] = fmaf(cf.K[j].z, xt[j], ut[2]);
+      ut[3] = fmaf(cf.K[j].w, xt[j], ut[3]);
+    }
+    if (l == 0) {
+      float* zt = zz[grp][0];
+      float* zr = zz[grp][1];
+      for (int i = 0; i < NX; ++i) zt[i] = xt[i];
+      for (int a4 = 0; a4 < NU; ++a4) zt[NX + a4] = ut[a4];
+      for (int i = 0; i < NZ; ++i) zr[i] = cf.zs[i];
+    }
+    lds_sync();
+    const float* zt = zz[grp][0];
+    const float* zr = zz[grp][1];
+    // entry l from lane l, entry 16 from every lane (the same value): no
+    // branch around the stores
+    A.gp[srow * NZ + l] = zt[l];
+    A.gp[srow * NZ + 16] = zt[16];
+    if (!DENSE) {
+      A.gQ[srow * NZ + l] = zt[l] * zr[l];
+      A.gQ[srow * NZ + 16] = zt[16] * zr[16];
+    } else {
+      for (int m = l; m < NPK; m += 16) {
+        const int i = c_pk_i[m], j = c_pk_j[m];
+        A.gQ[srow * NPK + m] = (i == j) ? zt[i] * zr[i] : zt[i] * zr[j] + zt[j] * zr[i];
+      }
+    }
+    lds_sync();
+    if constexpr (THETA) {
+      // row l of (C z~ + dL/dz*)_x and of (C z* + c)_x, then
+      // gth += ht^T xi_j + hs^T eta_j and one RK4 step of the sensitivities
+      float ht, hs;
+      if constexpr (DENSE) {
+        ht = cf.gl;
+        hs = cf.cl;
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+          ht = fmaf(cf.crow[c], xt[c], ht);
+          hs = fmaf(cf.crow[c], cf.zs[c], hs);
+        }
+#pragma unroll
+        for (int a4 = 0; a4 < NU; ++a4) {
+          ht = fmaf(cf.crow[NX + a4], ut[a4], ht);
+          hs = fmaf(cf.crow[NX + a4], cf.zs[NX + a4], hs);
+        }
+      } else {
+        float xl = xt[0], zl = cf.zs[0];
+#pragma unroll
+        for (int c = 1; c < NX; ++c) {
+          xl = (l == c) ? xt[c] : xl;
+          zl = (l == c) ? cf.zs[c] : zl;
+        }
+        ht = fmaf(cf.crow[0], xl, cf.gl);
+        hs = fmaf(cf.crow[0], zl, cf.cl);
+      }
+      float dot = 0.f;
+#pragma unroll
+      for (int k = 0; k < NX; ++k) {
+        // both broadcasts on every lane (a broadcast inside a lane-dependent
+        // branch would read lanes that the branch has switched off)
+        const float bt = rb(ht, k), bs = rb(hs, k);
+        dot = fmaf((l < 8) ? bt : bs, sv[k], dot);
+      }
+      gth += (double)dot;
+      if (t + 1 < T) {
+        if (l < 8) dmpc_theta::propagate_xi(PN, cf.zs, cf.zs + NX, sv);
+        else dmpc_theta::propagate_eta(PN, cf.zs, cf.zs + NX, xt, ut, sv);
+      }
+    }
+    if (t + 1 < T) {
+      float xi = 0.f;
+      if (l < NX) {
+#pragma unroll
+        for (int c = 0; c < NX; ++c) xi = fmaf(cf.fr[c], xt[c], xi);
+#pragma unroll
+        for (int a4 = 0; a4 < NU; ++a4) xi = fmaf(cf.fr[NX + a4], ut[a4], xi);
+      }
+#pragma unroll
+      for (int j = 0; j < NX; ++j) xt[j] = rb(xi, j);
+    }
+  };
+  FStage f0, f1;
   for (int sg = 0; sg < nseg; ++sg) {
     const int a = sg * seg, e = (a + seg < T) ? a + seg : T;
     if (CKPT) recompute(a, e);
-    fload(a, a, cf);
+    fload(a, a, f0);
     __builtin_amdgcn_s_waitcnt(0);  // no load pending on loop entry
-    for (int t = a; t < e; ++t) {
-      if (t + 1 < e) fload(t + 1, a, nf);
-      const size_t srow = (size_t)b * Tm + t;
-      float ut[4] = {cf.kk.x, cf.kk.y, cf.kk.z, cf.kk.w};
-#pragma unroll
-      for (int j = 0; j < NX; ++j) {
-        ut[0] = fmaf(cf.K[j].x, xt[j], ut[0]);
-        ut[1] = fmaf(cf.K[j].y, xt[j], ut[1]);
-        ut[2] = fmaf(cf.K[j].z, xt[j], ut[2]);
-        ut[3] = fmaf(cf.K[j].w, xt[j], ut[3]);
-      }
-      if (l == 0) {
-        float* zt = zz[grp][0];
-        float* zr = zz[grp][1];
-        for (int i = 0; i < NX; ++i) zt[i] = xt[i];
-        for (int a4 = 0; a4 < NU; ++a4) zt[NX + a4] = ut[a4];
-        for (int i = 0; i < NZ; ++i) zr[i] = cf.zs[i];
-      }
-      lds_sync();
-      const float* zt = zz[grp][0];
-      const float* zr = zz[grp][1];
-      for (int ee = l; ee < NZ; ee += 16) A.gp[srow * NZ + ee] = zt[ee];
-      if (!DENSE) {
-        for (int ee = l; ee < NZ; ee += 16) A.gQ[srow * NZ + ee] = zt[ee] * zr[ee];
-      } else {
-        for (int m = l; m < NPK; m += 16) {
-          const int i = c_pk_i[m], j = c_pk_j[m];
-          A.gQ[srow * NPK + m] = (i == j) ? zt[i] * zr[i] : zt[i] * zr[j] + zt[j] * zr[i];
-        }
-      }
-      lds_sync();
-      if constexpr (THETA) {
-        // row l of (C z~ + dL/dz*)_x and of (C z* + c)_x, then
-        // gth += ht^T xi_j + hs^T eta_j and one RK4 step of the sensitivities
-        float ht, hs;
-        if constexpr (DENSE) {
-          ht = cf.gl;
-          hs = cf.cl;
-#pragma unroll
-          for (int c = 0; c < NX; ++c) {
-            ht = fmaf(cf.crow[c], xt[c], ht);
-            hs = fmaf(cf.crow[c], cf.zs[c], hs);
-          }
-#pragma unroll
-          for (int a4 = 0; a4 < NU; ++a4) {
-            ht = fmaf(cf.crow[NX + a4], ut[a4], ht);
-            hs = fmaf(cf.crow[NX + a4], cf.zs[NX + a4], hs);
-          }
-        } else {
-          float xl = xt[0], zl = cf.zs[0];
-#pragma unroll
-          for (int c = 1; c < NX; ++c) {
-            xl = (l == c) ? xt[c] : xl;
-            zl = (l == c) ? cf.zs[c] : zl;
-          }
-          ht = fmaf(cf.crow[0], xl, cf.gl);
-          hs = fmaf(cf.crow[0], zl, cf.cl);
-        }
-        float dot = 0.f;
-#pragma unroll
-        for (int k = 0; k < NX; ++k) {
-          // both broadcasts on every lane (a broadcast inside a lane-dependent
-          // branch would read lanes that the branch has switched off)
-          const float bt = rb(ht, k), bs = rb(hs, k);
-          dot = fmaf((l < 8) ? bt : bs, sv[k], dot);
-        }
-        gth += (double)dot;
-        if (t + 1 < T) {
-          if (l < 8) dmpc_theta::propagate_xi(PN, cf.zs, cf.zs + NX, sv);
-          else dmpc_theta::propagate_eta(PN, cf.zs, cf.zs + NX, xt, ut, sv);
-        }
-      }
-      if (t + 1 < T) {
-        float xi = 0.f;
-        if (l < NX) {
-#pragma unroll
-          for (int c = 0; c < NX; ++c) xi = fmaf(cf.fr[c], xt[c], xi);
-#pragma unroll
-          for (int a4 = 0; a4 < NU; ++a4) xi = fmaf(cf.fr[NX + a4], ut[a4], xi);
-        }
-#pragma unroll
-        for (int j = 0; j < NX; ++j) xt[j] = rb(xi, j);
-      }
-      if (t + 1 < e) cf = nf;
+    for (int t = a; t < e; t += 2) {
+      fstep(t, a, e, f0, f1);
+      if (t + 1 >= e) break;
+      fstep(t + 1, a, e, f1, f0);
     }
   }
   for (int t = T; t < Tm; ++t) {
