@@ -438,7 +438,9 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
         }
     }
     lds_write<NX>(L + L_QX + l * 14, Qc);
-    if (!DENSE && l >= 1 && l < NX) L[L_QX + l * 15] += qdiag;
+    // this lane's diagonal entry of the block, read now and completed with the
+    // diagonal cost after the box-QP (the read's latency then hides behind it)
+    const double qdd = DENSE ? 0.0 : L[L_QX + l * 15];
     // Y[0, :] by lane (row 0 of Q without the cost), broadcast only after the
     // box-QP so that its 32 registers are free during the QP
     double y0b[16];
@@ -467,6 +469,12 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
       for (int a = 0; a < 4; ++a) fr[a] = (zb[NX + a] == G.lo[a] || zb[NX + a] == G.hi[a]) ? 0.0 : 1.0;
       chol4(H, fr, A.piv, C, st);
     }
+    // every lane writes its diagonal entry back (row 0 and rows 13..15 are not
+    // read below); then the rows of Q are read ahead of their use
+    if (!DENSE) L[L_QX + l * 15] = qdd + qdiag;
+    double Sq[NX];
+#pragma unroll
+    for (int j = 0; j < NX; ++j) Sq[j] = L[L_QX + l * 14 + j];
 
     bcast16(y0b, Yc[0]);
     // gain column: K[:, l] = -Qff^{-1} Q_ux[:, l] on the free rows, 0 on clamped rows
@@ -498,7 +506,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
       for (int a = 0; a < 4; ++a) vi = fma(Qux[a], kv[a], vi);
       double S[NX];
 #pragma unroll
-      for (int j = 0; j < NX; ++j) S[j] = (l == 0) ? R0r[j] : L[L_QX + l * 14 + j];
+      for (int j = 0; j < NX; ++j) S[j] = (l == 0) ? R0r[j] : Sq[j];
 #pragma unroll
       for (int a = 0; a < 4; ++a) v_block(S, Kd[a], Qux[a]);
       sfor<NX>([&](auto J) {
@@ -638,7 +646,8 @@ __device__ __forceinline__ void ls_stage(const KArgs& A, int b, int n, int t, in
                    : (r == 1 ? make_float4(x[4], x[5], x[6], x[7])
                    : (r == 2 ? make_float4(x[8], x[9], x[10], x[11]) : make_float4(x[12], 0.f, 0.f, 0.f)));
     *(float4*)(zo + 4 * r) = w;
-    if (r == 0) *(float4*)(zo + 16) = make_float4(z[13], z[14], z[15], z[16]);
+    // all four lanes write the same controls: no branch around the store
+    *(float4*)(zo + 16) = make_float4(z[13], z[14], z[15], z[16]);
   }
   if (t + 1 < T) rk4(A.P, x, z + NX, xn);
 }
