@@ -640,7 +640,7 @@ __device__ __forceinline__ void ls_stage(const KArgs& A, int b, int n, int t, in
     }
   }
   {
-    // lane r of the quad writes floats 4r..4r+3 of the stage record, lane 0 also the controls
+    // lane r of the quad writes floats 4r..4r+3 of the stage record
     float* zo = traj_at(A, b, sc, t);
     const float4 w = r == 0 ? make_float4(x[0], x[1], x[2], x[3])
                    : (r == 1 ? make_float4(x[4], x[5], x[6], x[7])
