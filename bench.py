@@ -62,12 +62,12 @@ def load_traffic(kernel_hash, B):
     return d.get("hbm_bytes_per_launch")
 
 
-def make_inputs(dev):
+def make_inputs(dev, B=None):
     import numpy as np
     import torch
 
     import workloads as W
-    d = W.make(2)
+    d = W.make(2) if B is None else W.make(2, B=B)
     t = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev) for k in ("x0", "Q", "p", "lo", "hi", "grad_u")}
     t["T"] = torch.from_numpy(d["T"]).to(dev)
     return d, t
@@ -357,6 +357,10 @@ def main():
     ap.add_argument("--closed-loop", action="store_true",
                     help="receding-horizon control-step latency at B=1 (T 10, 20, 50; fixed K=5 and K<=30 with "
                          "tol 1e-5; cold, warm, warm+graph); prints one JSON line with the table")
+    ap.add_argument("--shard", type=int, default=0, metavar="G",
+                    help="one GPU's share of the metric workload split over G GPUs (B = 4096 / G, T = 20): "
+                         "fwd+bwd step time of the tuned persistent form and of the per-launch form; prints one "
+                         "JSON line")
     ap.add_argument("--profile-short", action="store_true",
                     help="for counter collection: two direct fwd+bwd calls of the persistent form, then a "
                          "256 MiB device copy whose FETCH_SIZE / WRITE_SIZE calibrate the HBM counters")
@@ -373,6 +377,17 @@ def main():
         return
     if a.closed_loop:
         print(json.dumps({"closed_loop_latency": closed_loop_latency(), "workload": "hover_to_random_target, B=1"}),
+              flush=True)
+        return
+    if a.shard > 0:
+        Bs = 4096 // a.shard
+        d, t = make_inputs(dev, Bs)
+        res = run_gpu_bench(d, t, a.steps, a.warmup)
+        per, pl = res["persistent"], res["plain"]
+        print(json.dumps({"shard": dict(gpus=a.shard, B=Bs, T=d["T_max"], K=d["K"],
+                                        ms_per_step=per["s_per_step"] * 1e3, solves_per_s=Bs / per["s_per_step"],
+                                        fwd_ms=per["fwd_ms"], launch_choice=per["choice"],
+                                        plain_ms_per_step=pl["s_per_step"] * 1e3)}),
               flush=True)
         return
     print("bench: building inputs (B=4096, T=20, MLP cost)", file=sys.stderr, flush=True)
