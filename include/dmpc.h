@@ -85,8 +85,9 @@ extern "C" {
 #define DMPC_ST_CONVERGED 0x1u   /* tol_du > 0 and ||U^k - U^{k-1}||_inf < tol_du was reached */
 #define DMPC_ST_MAXITER 0x2u     /* tol_du > 0 and the iteration cap was hit first */
 #define DMPC_ST_NONFINITE 0x4u   /* a non-finite value appeared (all line-search costs non-finite) */
-#define DMPC_ST_FP64 0x8u        /* a stage Cholesky pivot fell below fp64_pivot (ill-conditioned stage;
-                                    the control block is always factored in FP64) */
+#define DMPC_ST_FP64 0x8u        /* a pivot of a stage's control-block factorisation fell below fp64_pivot
+                                    (ill-conditioned stage; the block is always factored in FP64, as
+                                    L D L^T, whose pivots D_i are the squares of Cholesky's) */
 #define DMPC_ST_QPMAXITER 0x10u  /* a stagewise box-QP hit its iteration cap */
 #define DMPC_ST_REGULARIZED 0x20u /* a non-positive pivot remained; the block was shifted */
 #define DMPC_ST_ITERS_SHIFT 8    /* bits 8..15: iLQR iterations performed */

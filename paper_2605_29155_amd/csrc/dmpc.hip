@@ -458,7 +458,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     }
 
     double kv[4] = {0.0, 0.0, 0.0, 0.0}, fr[4];
-    Chol4 C;
+    Fact4 C;
     float* gp = gains_at(A, b, t);
     if (MODE == 0) {
       double kw[4] = {0.0, 0.0, 0.0, 0.0};
@@ -467,7 +467,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     } else {
 #pragma unroll
       for (int a = 0; a < 4; ++a) fr[a] = (zb[NX + a] == G.lo[a] || zb[NX + a] == G.hi[a]) ? 0.0 : 1.0;
-      chol4(H, fr, A.piv, C, st);
+      ldl4(H, fr, A.piv, C, st);
     }
     // every lane writes its diagonal entry back (row 0 and rows 13..15 are not
     // read below); then the rows of Q are read ahead of their use
@@ -1373,7 +1373,7 @@ __global__ __launch_bounds__(64) void k_tpar_gains(KArgs A, int src) {
   }
   __syncthreads();  // every thread has read the previous feedforward before it is overwritten
   double kv[4], fr[4];
-  Chol4 Ch;
+  Fact4 Ch;
   uint32_t st = 0;
   boxqp(H, qu, dl, dh, kw, A.piv, kv, fr, Ch, st);
   unsigned code = 0;
@@ -1445,9 +1445,9 @@ __global__ __launch_bounds__(64) void k_tpar_tail(KArgs A, int src) {
     const float u = zb[NX + a];
     fr[a] = (u == A.lo[(size_t)b * 4 + a] || u == A.hi[(size_t)b * 4 + a]) ? 0.0 : 1.0;
   }
-  Chol4 Ch;
+  Fact4 Ch;
   uint32_t st = 0;
-  chol4(H, fr, A.piv, Ch, st);
+  ldl4(H, fr, A.piv, Ch, st);
   float* tp = tail_at(A, b, t);
   for (int idx = threadIdx.x; idx < NZ * NX; idx += 64) {
     const int c = idx / NX, r = idx % NX;

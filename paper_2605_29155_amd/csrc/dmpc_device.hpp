@@ -244,47 +244,46 @@ __device__ __forceinline__ void rk4_column(const Dyn& P, const float* x, const f
 }
 
 // ---------------------------------------------------------------------------
-// 4x4 control block: Cholesky of the free block (clamped rows/cols replaced by
-// identity) and the stagewise box-QP, in FP64.  The control block of the stage
+// 4x4 control block: LDL^T factorisation of the free block (clamped rows/cols
+// replaced by identity) and the stagewise box-QP, in FP64.  The control block of the stage
 // Hessian is ill-conditioned for these costs (collective thrust has curvature
 // ~R = 1e-2 next to torque curvature ~1e3 in rotor coordinates), so it is
 // accumulated and solved in double precision.
 // ---------------------------------------------------------------------------
 
-struct Chol4 {
-  double L[10];  // L00 L10 L11 L20 L21 L22 L30 L31 L32 L33
-  double iD[4];  // 1 / L_ii
+// H~ = L D L^T with L unit lower triangular
+struct Fact4 {
+  double L[10];  // D0 L10 D1 L20 L21 D2 L30 L31 L32 D3 (packed lower triangle, the pivots on the diagonal)
+  double iD[4];  // 1 / D_i
 };
 
-// 1/sqrt(d) and 1/d from the hardware estimates (relative error ~5e-8 on
-// gfx950) plus one Newton step (each step doubles the correct bits: ~4e-15
-// after one), instead of the IEEE divide/sqrt sequences; d > 0 for rsq.
-__device__ __forceinline__ double rsq_nr(double d) {
-  double y = __builtin_amdgcn_rsq(d);
-  const double hd = 0.5 * d;
-  y = fma(y, fma(-hd * y, y, 0.5), y);
-  return y;
-}
+// 1/d from the hardware estimate (relative error ~5e-8 on gfx950) plus one
+// Newton step (each step doubles the correct bits: ~4e-15 after one), instead
+// of the IEEE divide sequence
 __device__ __forceinline__ double rcp_nr(double d) {
   double r = __builtin_amdgcn_rcp(d);
   r = fma(r, fma(-d, r, 1.0), r);
   return r;
 }
 
-__device__ __forceinline__ bool chol4_core(const double* h, double* L, double* iD, double& dmin) {
+__device__ __forceinline__ bool ldl4_core(const double* h, double* L, double* iD, double& dmin) {
+  // LDL^T: u_ij = L_ij D_j are formed first, so each pivot's reciprocal is
+  // the only long-latency step on the chain
   const double d0 = h[0];
-  const double i0 = rsq_nr(d0 > 0.0 ? d0 : 1e-300), l00 = d0 * i0;
+  const double i0 = rcp_nr(d0 > 0.0 ? d0 : 1e-300);
   const double l10 = h[4] * i0, l20 = h[8] * i0, l30 = h[12] * i0;
-  const double d1 = h[5] - l10 * l10;
-  const double i1 = rsq_nr(d1 > 0.0 ? d1 : 1e-300), l11 = d1 * i1;
-  const double l21 = (h[9] - l20 * l10) * i1, l31 = (h[13] - l30 * l10) * i1;
-  const double d2 = h[10] - l20 * l20 - l21 * l21;
-  const double i2 = rsq_nr(d2 > 0.0 ? d2 : 1e-300), l22 = d2 * i2;
-  const double l32 = (h[14] - l30 * l20 - l31 * l21) * i2;
-  const double d3 = h[15] - l30 * l30 - l31 * l31 - l32 * l32;
-  const double i3 = rsq_nr(d3 > 0.0 ? d3 : 1e-300), l33 = d3 * i3;
-  L[0] = l00; L[1] = l10; L[2] = l11; L[3] = l20; L[4] = l21;
-  L[5] = l22; L[6] = l30; L[7] = l31; L[8] = l32; L[9] = l33;
+  const double d1 = h[5] - l10 * h[4];
+  const double i1 = rcp_nr(d1 > 0.0 ? d1 : 1e-300);
+  const double u21 = h[9] - l20 * h[4], u31 = h[13] - l30 * h[4];
+  const double l21 = u21 * i1, l31 = u31 * i1;
+  const double d2 = h[10] - l20 * h[8] - l21 * u21;
+  const double i2 = rcp_nr(d2 > 0.0 ? d2 : 1e-300);
+  const double u32 = h[14] - l30 * h[8] - l31 * u21;
+  const double l32 = u32 * i2;
+  const double d3 = h[15] - l30 * h[12] - l31 * u31 - l32 * u32;
+  const double i3 = rcp_nr(d3 > 0.0 ? d3 : 1e-300);
+  L[0] = d0; L[1] = l10; L[2] = d1; L[3] = l20; L[4] = l21;
+  L[5] = d2; L[6] = l30; L[7] = l31; L[8] = l32; L[9] = d3;
   iD[0] = i0; iD[1] = i1; iD[2] = i2; iD[3] = i3;
   const double m01 = d0 < d1 ? d0 : d1, m23 = d2 < d3 ? d2 : d3;
   dmin = m01 < m23 ? m01 : m23;
@@ -295,7 +294,7 @@ __device__ __forceinline__ bool chol4_core(const double* h, double* L, double* i
 // piv marks the stage ill-conditioned (ST_FP64); a pivot that is not positive
 // gets a diagonal shift of 1e-6 max(1, max diag) (x10 until it factors) and
 // ST_REGULARIZED.
-__device__ __forceinline__ void chol4(const double* H, const double* fr, float piv, Chol4& C, uint32_t& st) {
+__device__ __forceinline__ void ldl4(const double* H, const double* fr, float piv, Fact4& C, uint32_t& st) {
   double h[16];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -303,7 +302,7 @@ __device__ __forceinline__ void chol4(const double* H, const double* fr, float p
     for (int b = 0; b < 4; ++b)
       h[a * 4 + b] = (a == b) ? (fr[a] != 0.0 ? H[a * 4 + a] : 1.0) : fr[a] * fr[b] * H[a * 4 + b];
   double dmin;
-  bool ok = chol4_core(h, C.L, C.iD, dmin);
+  bool ok = ldl4_core(h, C.L, C.iD, dmin);
   if (piv > 0.f && !(dmin >= (double)piv)) st |= ST_FP64;
   if (!ok) {
     double mx = 1.0;
@@ -316,7 +315,7 @@ __device__ __forceinline__ void chol4(const double* H, const double* fr, float p
       for (int i = 0; i < 16; ++i) hs[i] = h[i];
 #pragma unroll
       for (int a = 0; a < 4; ++a) hs[a * 5] += shift;
-      ok = chol4_core(hs, C.L, C.iD, dmin);
+      ok = ldl4_core(hs, C.L, C.iD, dmin);
       shift *= 10.0;
     }
     st |= ST_REGULARIZED;
@@ -324,17 +323,17 @@ __device__ __forceinline__ void chol4(const double* H, const double* fr, float p
 }
 
 // r <- Htilde^{-1} r
-__device__ __forceinline__ void solve4(const Chol4& C, double* r) {
+__device__ __forceinline__ void solve4(const Fact4& C, double* r) {
   const double* L = C.L;
   const double* iD = C.iD;
-  const double z0 = r[0] * iD[0];
-  const double z1 = (r[1] - L[1] * z0) * iD[1];
-  const double z2 = (r[2] - L[3] * z0 - L[4] * z1) * iD[2];
-  const double z3 = (r[3] - L[6] * z0 - L[7] * z1 - L[8] * z2) * iD[3];
-  const double y3 = z3 * iD[3];
-  const double y2 = (z2 - L[8] * y3) * iD[2];
-  const double y1 = (z1 - L[4] * y2 - L[7] * y3) * iD[1];
-  const double y0 = (z0 - L[1] * y1 - L[3] * y2 - L[6] * y3) * iD[0];
+  const double w0 = r[0];
+  const double w1 = r[1] - L[1] * w0;
+  const double w2 = r[2] - L[3] * w0 - L[4] * w1;
+  const double w3 = r[3] - L[6] * w0 - L[7] * w1 - L[8] * w2;
+  const double y3 = w3 * iD[3];
+  const double y2 = w2 * iD[2] - L[8] * y3;
+  const double y1 = w1 * iD[1] - L[4] * y2 - L[7] * y3;
+  const double y0 = w0 * iD[0] - L[1] * y1 - L[3] * y2 - L[6] * y3;
   r[0] = y0; r[1] = y1; r[2] = y2; r[3] = y3;
 }
 
@@ -378,7 +377,7 @@ __device__ __forceinline__ bool qp_clamped(double x, double g, double lo, double
 // On return x is the step, fr the free mask (1/0) and C the factor of the free
 // block for that mask.
 __device__ __forceinline__ void boxqp(const double* H, const double* q, const double* lo, const double* hi,
-                                      const double* xw, float piv, double* x, double* fr, Chol4& C, uint32_t& st) {
+                                      const double* xw, float piv, double* x, double* fr, Fact4& C, uint32_t& st) {
   double g[4];
   bool W[4];
 #pragma unroll
@@ -390,7 +389,7 @@ __device__ __forceinline__ void boxqp(const double* H, const double* q, const do
   for (int it = 0; it < 16 && !done; ++it) {
 #pragma unroll
     for (int a = 0; a < 4; ++a) fr[a] = W[a] ? 0.0 : 1.0;
-    chol4(H, fr, piv, C, st);
+    ldl4(H, fr, piv, C, st);
     double d[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) d[a] = -fr[a] * g[a];
@@ -446,7 +445,7 @@ __device__ __forceinline__ void boxqp(const double* H, const double* q, const do
   if (!done) {
 #pragma unroll
     for (int a = 0; a < 4; ++a) fr[a] = W[a] ? 0.0 : 1.0;
-    chol4(H, fr, piv, C, st);
+    ldl4(H, fr, piv, C, st);
 #pragma unroll
     for (int a = 0; a < 4; ++a) x[a] = clampd(x[a], lo[a], hi[a]);
     st |= ST_QPMAXITER;
