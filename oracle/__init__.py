@@ -21,7 +21,6 @@ DYN_QUAD, DYN_AFFINE = 0, 1
 ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_QPFAIL, ST_REGULARIZED = 0x1, 0x2, 0x4, 0x10, 0x20
 FREE, LOWER, UPPER = 0, 1, 2
 ALPHA_NONE = 255
-ALPHAS = (1.0, 0.5, 0.25, 0.1)
 
 
 class Params(C.Structure):
@@ -45,6 +44,14 @@ def lib():
             _build.build()
         _lib = C.CDLL(path)
     return _lib
+
+
+def alphas():
+    """The C oracle's line-search step lengths, in the order it tries them
+    (Sec. IV "Forward pass with line-search")."""
+    out = np.zeros(NALPHA)
+    n = lib().orc_alphas(_ptr(out))
+    return tuple(float(a) for a in out[:n])
 
 
 def params(mass=0.75, Jxx=2.5e-3, Jyy=2.5e-3, Jzz=4.5e-3, arm=0.15, kappa=0.01, dt=0.05, g=9.81):
@@ -126,7 +133,10 @@ def forward(P, x0, Q, p, lo, hi, T=None, K=5, tol=0.0, affine=None, u_init=None,
 
     affine = (A [B,T,13,13], Bm [B,T,13,4], r [B,T,13]) selects the affine
     dynamics; replay = (iters [B], alpha [B,K], pattern [B,K,T]) replays
-    another solver's decisions."""
+    another solver's decisions, and then out["replay_viol"] [B,K,T] scores
+    each replayed clamp pattern against the oracle's own stage QP (0 when it
+    satisfies the QP's optimality conditions, else the smallest relative
+    tolerance at which it would)."""
     x0, p, lo, hi = _d(x0), _d(p), _d(lo), _d(hi)
     Q = _d(Q)
     B, Tm = p.shape[0], p.shape[1]
@@ -147,13 +157,14 @@ def forward(P, x0, Q, p, lo, hi, T=None, K=5, tol=0.0, affine=None, u_init=None,
         assert ra.shape == (B, K) and rp.shape == (B, K, Tm)
     out = dict(u=np.zeros((B, Tm, NU)), x=np.zeros((B, Tm, NX)), J=np.zeros(B), iters=np.zeros(B, np.int32),
                status=np.zeros(B, np.uint32), alpha=np.zeros((B, K), np.uint8),
-               pattern=np.zeros((B, K, Tm), np.uint8), cand_cost=np.zeros((B, K, NALPHA)))
+               pattern=np.zeros((B, K, Tm), np.uint8), cand_cost=np.zeros((B, K, NALPHA)),
+               replay_viol=np.zeros((B, K, Tm)))
     rc = lib().orc_forward(
         C.byref(cfg), C.byref(P), _ptr(x0), _ptr(Q), _ptr(p), _ptr(lo), _ptr(hi), _ptr(Tarr, C.c_int32),
         _ptr(Aff), _ptr(Bff), _ptr(rff), _ptr(ui), _ptr(ri, C.c_int32), _ptr(ra, C.c_uint8), _ptr(rp, C.c_uint8),
         _ptr(out["u"]), _ptr(out["x"]), _ptr(out["J"]), _ptr(out["iters"], C.c_int32),
         _ptr(out["status"], C.c_uint32), _ptr(out["alpha"], C.c_uint8), _ptr(out["pattern"], C.c_uint8),
-        _ptr(out["cand_cost"]))
+        _ptr(out["cand_cost"]), _ptr(out["replay_viol"]))
     if rc != 0:
         raise ValueError("orc_forward rejected its arguments")
     return out

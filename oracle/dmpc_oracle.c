@@ -85,6 +85,13 @@ typedef struct {
 
 static const double kAlphas[ORC_NALPHA] = {1.0, 0.5, 0.25, 0.1};
 
+int orc_alphas(double* out) {
+  int i;
+  if (out)
+    for (i = 0; i < ORC_NALPHA; ++i) out[i] = kAlphas[i];
+  return ORC_NALPHA;
+}
+
 /* ------------------------------------------------------------------------ */
 /* dynamics and its derivatives                                             */
 /* ------------------------------------------------------------------------ */
@@ -226,6 +233,36 @@ static void qp_pattern_solve(const double* H, const double* q, const double* a, 
   chol_sub(H, NU, idx, nf, L, flags);
   chol_solve(L, nf, rhs);
   for (i = 0; i < nf; ++i) d[idx[i]] = rhs[i];
+}
+
+/* How far a pattern's solution d (from qp_pattern_solve) is from the
+ * optimality conditions of the stagewise box-QP that orc_boxqp enforces: a
+ * free coordinate inside [a, b], a coordinate on its lower (upper) bound with
+ * a non-negative (non-positive) multiplier g = H d + q.  Returned as the
+ * smallest relative tolerance at which every condition holds, in orc_boxqp's
+ * scaling (free: violation / (1 + |d_i|); clamped: wrong-signed g_i over the
+ * magnitude |q_i| + sum_j |H_ij d_j| of its terms); 0 for a valid pattern.  A
+ * coordinate with a_i = b_i is fixed whichever bound the pattern names. */
+static double pattern_violation(const double* H, const double* q, const double* a, const double* b,
+                                const int32_t* pat, const double* d) {
+  double worst = 0.0;
+  int i, j;
+  for (i = 0; i < NU; ++i) {
+    double g = q[i], mag = fabs(q[i]), v = 0.0;
+    for (j = 0; j < NU; ++j) {
+      g += H[i * NU + j] * d[j];
+      mag += fabs(H[i * NU + j] * d[j]);
+    }
+    if (pat[i] == ORC_FREE) {
+      const double out = d[i] < a[i] ? a[i] - d[i] : (d[i] > b[i] ? d[i] - b[i] : 0.0);
+      v = out / (1.0 + fabs(d[i]));
+    } else if (a[i] < b[i]) {
+      const double wrong = (pat[i] == ORC_LOWER) ? -g : g;
+      v = wrong > 0.0 ? wrong / (mag > 0.0 ? mag : 1e-300) : 0.0;
+    }
+    if (!(v <= worst)) worst = v; /* a NaN propagates */
+  }
+  return worst;
 }
 
 uint32_t orc_boxqp(const double* H, const double* q, const double* a, const double* b, double* d,
@@ -502,6 +539,7 @@ typedef struct {
   uint8_t* alpha_log;   /* K or NULL */
   uint8_t* pattern_log; /* K*Tmax or NULL */
   double* cand_cost;    /* K*4 or NULL */
+  double* replay_viol;  /* K*Tmax or NULL: pattern_violation of each replayed stage pattern */
 } ilqr_io;
 
 static void ilqr_one(const inst_t* in, ilqr_io* io) {
@@ -564,6 +602,9 @@ static void ilqr_one(const inst_t* in, ilqr_io* io) {
           uint8_t code = io->replay_pattern[(size_t)k * io->Tmax + t];
           for (i = 0; i < NU; ++i) pat[i] = (code >> (2 * i)) & 3;
           qp_pattern_solve(H, qu, a, b, pat, d, &io->status);
+          /* score the replayed pattern against this stage's own QP before the
+           * step is clamped into the box (the clamp would hide a wrong one) */
+          if (io->replay_viol) io->replay_viol[(size_t)k * io->Tmax + t] = pattern_violation(H, qu, a, b, pat, d);
           for (i = 0; i < NU; ++i) d[i] = clampd(d[i], a[i], b[i]);
         } else {
           io->status |= orc_boxqp(H, qu, a, b, d, pat);
@@ -850,7 +891,7 @@ typedef struct {
   /* forward */
   const int32_t* replay_iters;
   const uint8_t *replay_alpha, *replay_pattern;
-  double *u_out, *x_out, *J_out, *cand_cost;
+  double *u_out, *x_out, *J_out, *cand_cost, *replay_viol;
   int32_t* iters_out;
   uint32_t* status_out;
   uint8_t *alpha_log, *pattern_log;
@@ -912,6 +953,11 @@ static void* fwd_worker(void* arg) {
     io.alpha_log = jb->alpha_log ? jb->alpha_log + (size_t)b * K : NULL;
     io.pattern_log = jb->pattern_log ? jb->pattern_log + (size_t)b * K * Tm : NULL;
     io.cand_cost = jb->cand_cost ? jb->cand_cost + (size_t)b * K * ORC_NALPHA : NULL;
+    io.replay_viol = (jb->replay_viol && io.replay) ? jb->replay_viol + (size_t)b * K * Tm : NULL;
+    if (jb->replay_viol) {
+      int i;
+      for (i = 0; i < K * Tm; ++i) jb->replay_viol[(size_t)b * K * Tm + i] = 0.0;
+    }
     if (io.alpha_log) memset(io.alpha_log, ORC_ALPHA_NONE, (size_t)K);
     if (io.pattern_log) memset(io.pattern_log, 0, (size_t)K * Tm);
     if (io.cand_cost) {
@@ -1047,7 +1093,7 @@ int orc_forward(const orc_config* cfg, const orc_params* P, const double* x0, co
                 const double* Aff, const double* Bff, const double* rff, const double* u_init,
                 const int32_t* replay_iters, const uint8_t* replay_alpha, const uint8_t* replay_pattern,
                 double* u_out, double* x_out, double* J_out, int32_t* iters_out, uint32_t* status_out,
-                uint8_t* alpha_log, uint8_t* pattern_log, double* cand_cost) {
+                uint8_t* alpha_log, uint8_t* pattern_log, double* cand_cost, double* replay_viol) {
   job_t jb;
   if (check_cfg(cfg)) return -1;
   if (cfg->dyn_kind == ORC_DYN_AFFINE && (!Aff || !Bff || !rff)) return -1;
@@ -1076,6 +1122,7 @@ int orc_forward(const orc_config* cfg, const orc_params* P, const double* x0, co
   jb.alpha_log = alpha_log;
   jb.pattern_log = pattern_log;
   jb.cand_cost = cand_cost;
+  jb.replay_viol = replay_viol;
   return run_jobs(&jb, fwd_worker);
 }
 

@@ -81,6 +81,11 @@ typedef struct {
 
 /* ---- single-instance building blocks (pinned directly by tests) ---- */
 
+/* The line-search step lengths the forward tries, in the order it tries them
+ * (Sec. IV "Forward pass with line-search"): writes ORC_NALPHA values to out
+ * (when not NULL) and returns ORC_NALPHA. */
+int orc_alphas(double* out);
+
 /* continuous-time right-hand side xdot = F(x, u) */
 void orc_dyn(const orc_params* P, const double* x, const double* u, double* xdot);
 /* one RK4 step x_next = f(x, u) */
@@ -116,14 +121,19 @@ int orc_lu_solve(int n, double* M, double* r);
  *   pattern per stage (2 bits per control, control i at bits 2i..2i+1).
  * Outputs (any may be NULL): u_out, x_out, J_out [B], iters_out [B],
  *   status_out [B], alpha_log [B][K], pattern_log [B][K][T_max],
- *   cand_cost [B][K][4] line-search costs J(alpha).
+ *   cand_cost [B][K][4] line-search costs J(alpha), replay_viol [B][K][T_max]
+ *   (replay only, else zero): how far each replayed stage pattern is from
+ *   the optimality conditions of the oracle's own stagewise box-QP (free
+ *   coordinates inside the box, multipliers of clamped ones correctly
+ *   signed), as the smallest relative tolerance at which they hold (0 for a
+ *   valid pattern), taken before the replayed step is clamped into the box.
  */
 int orc_forward(const orc_config* cfg, const orc_params* P, const double* x0, const double* Q,
                 const double* p, const double* lo, const double* hi, const int32_t* T,
                 const double* Aff, const double* Bff, const double* rff, const double* u_init,
                 const int32_t* replay_iters, const uint8_t* replay_alpha, const uint8_t* replay_pattern,
                 double* u_out, double* x_out, double* J_out, int32_t* iters_out, uint32_t* status_out,
-                uint8_t* alpha_log, uint8_t* pattern_log, double* cand_cost);
+                uint8_t* alpha_log, uint8_t* pattern_log, double* cand_cost, double* replay_viol);
 
 /* ---- batched backward: implicit differentiation at (x*, u*) ----
  * method 0: Riccati adjoint (an LQR solve with the active controls fixed);

@@ -9,9 +9,13 @@ On affine dynamics the OCP of eq. (3) is a convex QP, so:
   * the Riccati-adjoint backward must equal the dense KKT backward.
 """
 import itertools
+import json
+import os
 
 import numpy as np
 import pytest
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
 
 
 def affine_problem(rng, B, T, dense=False, bound=None, pu=1.0):
@@ -168,6 +172,115 @@ def test_riccati_adjoint_equals_dense_kkt_quadrotor(orc, P):
     r1 = orc.backward(*args, method=1)
     for k in ("dQ", "dp", "dx0"):
         assert np.abs(r0[k] - r1[k]).max() <= 1e-10 * max(1, np.abs(r1[k]).max()), k
+
+
+def kkt_optimum(pr, b, T):
+    """The unconstrained optimum of instance b over its first T stages (dense
+    equality-constrained KKT solve, numpy) as z [T, 17]."""
+    A, Bm, r = (a[b] for a in pr["affine"])
+    nz, nc = 17 * T, 13 * T
+    M = np.zeros((nz + nc, nz + nc))
+    rhs = np.zeros(nz + nc)
+    for t in range(T):
+        M[17 * t:17 * t + 17, 17 * t:17 * t + 17] = full_cost(pr["Q"][b, t])
+        rhs[17 * t:17 * t + 17] = -pr["p"][b, t]
+    G = np.zeros((nc, nz))
+    h = np.zeros(nc)
+    G[0:13, 0:13] = np.eye(13)
+    h[0:13] = pr["x0"][b]
+    for t in range(T - 1):
+        rw = 13 * (t + 1)
+        G[rw:rw + 13, 17 * (t + 1):17 * (t + 1) + 13] = np.eye(13)
+        G[rw:rw + 13, 17 * t:17 * t + 13] = -A[t]
+        G[rw:rw + 13, 17 * t + 13:17 * t + 17] = -Bm[t]
+        h[rw:rw + 13] = r[t]
+    M[nz:, :nz] = G
+    M[:nz, nz:] = G.T
+    rhs[nz:] = h
+    return np.linalg.solve(M, rhs)[:nz].reshape(T, 17)
+
+
+def objective(pr, b, z):
+    """Eq. (3)'s objective sum_t 1/2 z_t^T C_t z_t + c_t^T z_t over the rows of z."""
+    return sum(0.5 * z[t] @ full_cost(pr["Q"][b, t]) @ z[t] + pr["p"][b, t] @ z[t] for t in range(len(z)))
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_line_search_costs_follow_the_newton_parabola(orc, P, dense):
+    """Line search (Sec. IV "Forward pass with line-search") on an unbounded
+    affine problem, one iteration from a random U^0.  The backward pass then
+    gives the exact Newton step dz to the optimum, and the candidate with step
+    length alpha is the trajectory z0 + alpha dz (the feedback term follows
+    the state deviation, which is alpha dx by linearity).  Since the optimum
+    makes the derivative of J(z0 + alpha dz) vanish at alpha = 1, the cost of
+    the candidate is J0 + (J1 - J0)(2 alpha - alpha^2), with J0 the cost of
+    U^0's rollout and J1 the optimal cost, both evaluated here in numpy.
+    Pins the oracle's step lengths (against the paper's list), the 1/2 and
+    the range of stages of its cost.  Ragged horizons with non-zero cost
+    data past T_b: those stages must not count."""
+    alphas = np.array(GOLD["line_search_alphas"])
+    rng = np.random.default_rng(31 + dense)
+    B, Tm = 3, 7
+    pr = affine_problem(rng, B, Tm, dense=dense)
+    T = np.array([7, 5, 1], np.int32)
+    u0 = rng.normal(size=(B, Tm, 4))
+    f = orc.forward(P, pr["x0"], pr["Q"], pr["p"], pr["lo"], pr["hi"], T, K=1, affine=pr["affine"], u_init=u0)
+    f0 = orc.forward(P, pr["x0"], pr["Q"], pr["p"], pr["lo"], pr["hi"], T, K=0, affine=pr["affine"], u_init=u0)
+    for b in range(B):
+        Tb = int(T[b])
+        A, Bm, r = (a[b] for a in pr["affine"])
+        x, z0 = pr["x0"][b], []
+        for t in range(Tb):
+            z0.append(np.concatenate([x, u0[b, t]]))
+            x = A[t] @ x + Bm[t] @ u0[b, t] + r[t]
+        J0 = objective(pr, b, np.array(z0))
+        J1 = objective(pr, b, kkt_optimum(pr, b, Tb))
+        assert abs(f0["J"][b] - J0) <= 1e-10 * max(1.0, abs(J0))
+        want = J0 + (J1 - J0) * (2 * alphas - alphas ** 2)
+        scale = max(1.0, abs(J0), abs(J1))
+        assert np.abs(f["cand_cost"][b, 0] - want).max() <= 1e-9 * scale, (b, f["cand_cost"][b, 0], want)
+        assert f["alpha"][b, 0] == 0 and abs(f["J"][b] - J1) <= 1e-9 * scale
+
+
+def test_replay_check_accepts_valid_and_flags_wrong_patterns(orc, P):
+    """The replay of another solver's box-QP decisions scores each pattern
+    against the oracle's own stage QP: the oracle's own patterns score 0, and
+    a pattern with one coordinate wrongly put on a bound, or wrongly released
+    from one, is flagged (the replay still clamps that step into the box, so
+    the trajectory alone would not show it)."""
+    import workloads as W
+    d = W.make(0, pu_scale=0.01, seed=2000)
+    f = orc.forward(P, d["x0"], d["Q"], d["p"], d["lo"], d["hi"], d["T"], K=5)
+    rep = (f["iters"], f["alpha"], f["pattern"])
+    g = orc.forward(P, d["x0"], d["Q"], d["p"], d["lo"], d["hi"], d["T"], K=5, replay=rep)
+    assert np.array_equal(g["u"], f["u"]) and g["replay_viol"].max() <= 1e-9
+    codes = f["pattern"]
+    planted = 0
+    for kind in ("clamp_free", "free_clamped"):
+        bad = codes.copy()
+        hit = None
+        for b, k, t in zip(*np.nonzero(np.ones(codes.shape, bool))):
+            if k >= f["iters"][b] or t >= d["T"][b]:
+                continue
+            c = int(codes[b, k, t])
+            for i in range(4):
+                ci = (c >> (2 * i)) & 3
+                if kind == "clamp_free" and ci == 0:
+                    bad[b, k, t] = c | (1 << (2 * i))   # free -> lower bound
+                    hit = (b, k, t)
+                elif kind == "free_clamped" and ci != 0:
+                    bad[b, k, t] = c & ~(3 << (2 * i))  # clamped -> free
+                    hit = (b, k, t)
+                if hit:
+                    break
+            if hit:
+                break
+        assert hit is not None, kind
+        h = orc.forward(P, d["x0"], d["Q"], d["p"], d["lo"], d["hi"], d["T"], K=5,
+                        replay=(f["iters"], f["alpha"], bad))
+        assert h["replay_viol"][hit] > 1e-3, (kind, h["replay_viol"][hit])
+        planted += 1
+    assert planted == 2
 
 
 def test_line_search_takes_first_minimiser(orc, P):

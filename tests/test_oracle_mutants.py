@@ -41,6 +41,21 @@ MUTANTS = [
     ("theta_solution_costate_transposed", SRC, "gs += A[k * NX + i] * ls[k];", "gs += A[i * NX + k] * ls[k];"),
     ("theta_zt_stage_index", SRC, "for (k = 0; k < NX; ++k) fz += Ac[i * NX + k] * zt[t * NZ + k];",
      "for (k = 0; k < NX; ++k) fz += Ac[i * NX + k] * zt[(t + 1) * NZ + k];"),
+    # line search (Sec. IV "Forward pass with line-search") and the objective of eq. (3)
+    ("alpha_0125", SRC, "{1.0, 0.5, 0.25, 0.1};", "{1.0, 0.5, 0.25, 0.125};"),
+    ("stage_cost_drops_half", SRC, "J += 0.5 * z[i] * s + c[i] * z[i];", "J += z[i] * s + c[i] * z[i];"),
+    ("cost_drops_last_stage", SRC, "for (t = 0; t < in->T; ++t) J += stage_cost(",
+     "for (t = 0; t + 1 < in->T; ++t) J += stage_cost("),
+    ("cost_counts_last_stage_twice", SRC,
+     "  for (t = 0; t < in->T; ++t) J += stage_cost(in->C + (size_t)t * NZ * NZ, in->c + t * NZ, X + t * NX, U + t * NU);",
+     "  for (t = 0; t < in->T; ++t) J += stage_cost(in->C + (size_t)t * NZ * NZ, in->c + t * NZ, X + t * NX, U + t * NU);"
+     " if (in->T > 0) J += stage_cost(in->C + (size_t)(in->T - 1) * NZ * NZ, in->c + (in->T - 1) * NZ,"
+     " X + (in->T - 1) * NX, U + (in->T - 1) * NU);"),
+    # the check of replayed box-QP patterns
+    ("replay_check_multiplier_sign", SRC, "const double wrong = (pat[i] == ORC_LOWER) ? -g : g;",
+     "const double wrong = (pat[i] == ORC_LOWER) ? g : -g;"),
+    ("replay_check_ignores_box", SRC,
+     "const double out = d[i] < a[i] ? a[i] - d[i] : (d[i] > b[i] ? d[i] - b[i] : 0.0);", "const double out = 0.0;"),
 ]
 
 
@@ -58,7 +73,7 @@ def test_pins_catch_mutant(name, path, orig, mut):
         subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-o", lib,
                         os.path.join(td, "dmpc_oracle.c"), "-lm", "-lpthread"], check=True)
         env = dict(os.environ, DMPC_ORACLE_LIB=lib)
-        pins = ["tests/test_oracle_dynamics.py", "tests/test_oracle_boxqp.py", "tests/test_oracle_lqr.py",
+        pins = ["tests/test_golden.py", "tests/test_oracle_dynamics.py", "tests/test_oracle_boxqp.py", "tests/test_oracle_lqr.py",
                 "tests/test_oracle_grad.py", "tests/test_oracle_theta.py"]
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"] + pins,
                            cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
