@@ -230,7 +230,7 @@ def shift_warm_start(u, T=None):
 
 
 def receding_horizon(P, x0, cost, lo, hi, steps, T=None, K=5, tol=0.0, warm=True, plant=None, affine=None):
-    """Closed-loop MPC (Alg. 1/2 outer loop, Sec. II): at each step solve the
+    """Closed-loop MPC (Sec. III-A; the outer loops of Alg. 1 and Alg. 2): at each step solve the
     horizon problem from the current state, apply the first control of the
     solution to the plant, and repeat from the state reached.
 

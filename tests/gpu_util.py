@@ -25,6 +25,59 @@ def rel(a, b, axis_from=1):
     return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-6)
 
 
+def maxabs(a, b):
+    """Per-instance element-wise error max_i |a_i - b_i| / max(1, max_i |b_i|)."""
+    a = np.asarray(a, np.float64).reshape(a.shape[0], -1)
+    b = np.asarray(b, np.float64).reshape(b.shape[0], -1)
+    return np.abs(a - b).max(axis=1) / np.maximum(1.0, np.abs(b).max(axis=1))
+
+
+def replay_violation(o):
+    """Per-instance worst score of the kernel's clamp patterns, replayed by the
+    oracle, against the oracle's own stage QPs (Sec. IV, backward pass with
+    input bounds): 0 when every replayed pattern satisfies the QP's optimality
+    conditions (free controls inside the box, clamped ones with correctly
+    signed multipliers), else the smallest relative tolerance at which all do."""
+    v = o["replay"]["replay_viol"]
+    return v.reshape(v.shape[0], -1).max(axis=1)
+
+
+# bars of the parity tests: 1e-4 relative on u*, 1e-3 on the gradients, both
+# normwise per instance and element-wise (max-abs over max(1, max |ref|));
+# the replayed clamp patterns must satisfy the oracle's stage QPs to 1e-4
+TOL_U, TOL_G, TOL_VIOL = 1e-4, 1e-3, 1e-4
+GRADS = ("dQ", "dp", "dx0")
+
+
+def parity_errors(g, o, idx=None):
+    """Per-instance errors of the kernel's outputs g (rows idx) against the
+    oracle o that replayed its decisions on those rows: u (normwise), u_abs
+    (element-wise), g and g_abs (worst of dQ, dp, dx0), viol (replayed
+    patterns against the oracle's stage QPs)."""
+    sel = slice(None) if idx is None else idx
+    e = dict(u=rel(g["u"][sel], o["replay"]["u"]), u_abs=maxabs(g["u"][sel], o["replay"]["u"]),
+             viol=replay_violation(o))
+    if "bwd" in o and "dQ" in g:
+        e["g"] = np.max([rel(g[k][sel], o["bwd"][k]) for k in GRADS], axis=0)
+        e["g_abs"] = np.max([maxabs(g[k][sel], o["bwd"][k]) for k in GRADS], axis=0)
+    return e
+
+
+def within_bars(e, scale=1.0):
+    """Per-instance: every error of parity_errors within its bar (times scale)."""
+    ok = (e["u"] <= TOL_U * scale) & (e["u_abs"] <= TOL_U * scale) & (e["viol"] <= TOL_VIOL * scale)
+    if "g" in e:
+        ok &= (e["g"] <= TOL_G * scale) & (e["g_abs"] <= TOL_G * scale)
+    return ok
+
+
+def describe(e):
+    s = "u* %.2e (abs %.2e)" % (e["u"].max(), e["u_abs"].max())
+    if "g" in e:
+        s += " | grads %.2e (abs %.2e)" % (e["g"].max(), e["g_abs"].max())
+    return s + " | pattern violation %.1e" % e["viol"].max()
+
+
 def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=True, grad_u=None, grad_x=None,
             fp64_pivot=1e-6, ckpt=0, theta=False, tpar=False):
     import torch
@@ -68,9 +121,9 @@ def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=Tru
     return out
 
 
-def oracle_replay(d, g, idx=None, grad_u=None, grad_x=None):
-    """FP64 oracle on the same inputs, replaying the kernel's decisions; also a
-    free oracle run for the decision-agreement rate."""
+def oracle_replay(d, g, idx=None, grad_u=None, grad_x=None, free=True):
+    """FP64 oracle on the same inputs, replaying the kernel's decisions; also
+    (free=True) a free oracle run for the decision-agreement rate."""
     P = orc.params_from(W.quad_params_f32())
     sel = slice(None) if idx is None else idx
     x0, Q, p, lo, hi, T = (np.asarray(d[k])[sel] for k in ("x0", "Q", "p", "lo", "hi", "T"))
@@ -81,7 +134,7 @@ def oracle_replay(d, g, idx=None, grad_u=None, grad_x=None):
     dl = g["dlog"][sel]
     alpha, pattern = dl[:, :K, 0], dl[:, :K, 1:]
     fr = orc.forward(P, x0, Q, p, lo, hi, T, K=K, replay=(iters, alpha, pattern))
-    ff = orc.forward(P, x0, Q, p, lo, hi, T, K=K, tol=d["tol"])
+    ff = orc.forward(P, x0, Q, p, lo, hi, T, K=K, tol=d["tol"]) if free else None
     out = dict(replay=fr, free=ff, iters=iters, alpha=alpha, pattern=pattern)
     if "dQ" in g:
         mask = orc.active_mask(g["u"][sel], lo, hi, T)
@@ -121,20 +174,22 @@ def alpha_choices_valid(o, rtol=1e-4):
     return bad
 
 
-def oracle_sensitivity(d, o, idx=None, trials=3, eps=1e-7, seed=0):
+def oracle_sensitivity(d, o, idx=None, orows=None, trials=3, eps=1e-7, seed=0):
     """Conditioning of each instance's solution map at FP32 resolution: the
     largest normwise change of the FP64 oracle's u* (decisions replayed from
     the kernel) when Q, p and x0 get independent relative perturbations of
     size eps (about one FP32 rounding).  A kernel that rounds to FP32 at every
     stage of every iteration cannot agree with the oracle much better than
-    this on an instance where it is large."""
+    this on an instance where it is large.  idx: rows of d; orows: the rows
+    of o that belong to them (default all of o)."""
     P = orc.params_from(W.quad_params_f32())
     sel = slice(None) if idx is None else idx
     x0, Q, p, lo, hi, T = (np.asarray(d[k])[sel].astype(np.float64) for k in ("x0", "Q", "p", "lo", "hi", "T"))
     T = T.astype(np.int32)
-    rep = (o["iters"], o["alpha"], o["pattern"])
+    osel = slice(None) if orows is None else orows
+    rep = (o["iters"][osel], o["alpha"][osel], o["pattern"][osel])
     K = o["alpha"].shape[1]
-    base = o["replay"]["u"]
+    base = o["replay"]["u"][osel]
     rng = np.random.default_rng(seed)
     s = np.zeros(len(base))
     for _ in range(trials):

@@ -12,7 +12,8 @@ import pytest
 import oracle as orc
 import workloads as W
 
-from gpu_util import handle, oracle_replay, oracle_sensitivity, rel, run_gpu
+from gpu_util import (alpha_choices_valid, decision_agreement, describe, handle, oracle_replay, oracle_sensitivity,
+                      parity_errors, rel, run_gpu, within_bars)
 
 pytestmark = pytest.mark.gpu
 
@@ -49,9 +50,10 @@ def test_autograd_function_matches_raw_backward_and_oracle():
     assert np.array_equal(g["dx0"], x0.grad.cpu().numpy())
     # and the oracle (decisions replayed)
     o = oracle_replay(dd, g, grad_u=grad_u)
-    for k in ("dQ", "dp", "dx0"):
-        assert rel(g[k], o["bwd"][k]).max() <= 1e-3, k
-    assert rel(g["u"], o["replay"]["u"]).max() <= 1e-4
+    e = parity_errors(g, o)
+    print("cfg2 B=256 through the layer: %s" % describe(e), flush=True)
+    assert np.all(within_bars(e)), describe(e)
+    assert alpha_choices_valid(o) == 0
     # gradients reached the MLP weights
     assert all(prm.grad is not None and torch.isfinite(prm.grad).all() for prm in mlp.params)
 
@@ -186,32 +188,40 @@ def test_error_codes():
     torch.cuda.synchronize()
 
 
-def test_cfg3_full_size_ragged_sampled():
+def test_cfg3_full_size_ragged_all_instances():
     """Ragged batch, T in {10..50}, up to 10 iterations with the ||du||_inf
-    stop.  Almost no instance converges in 10 iterations at these horizons,
-    and the 10th iterate of a long unconverged iLQR run can be very sensitive
-    to rounding: on a few instances the FP64 oracle itself moves by up to
-    ~1e-4 when its inputs are perturbed at FP32 resolution.  The bars are
-    therefore 1e-4 (u*) and 1e-3 (gradients) scaled by max(1, s_b / 1e-6),
-    where s_b is that measured sensitivity (1e-6 = ten times the perturbation,
-    the amplification of a well-conditioned instance); at least 99% of the
-    sample must meet the unscaled bars."""
+    stop, every one of the 8192 instances against the oracle.  Almost no
+    instance converges in 10 iterations at these horizons, and the 10th
+    iterate of a long unconverged iLQR run can be very sensitive to rounding:
+    on a few instances the FP64 oracle itself moves by up to ~1e-4 when its
+    inputs are perturbed at FP32 resolution (1e-7 relative).  The CPU
+    emulation of the forward's arithmetic traces the kernel's error there to
+    its FP32 dynamics (linearisation and rollout together).  So: at least 99%
+    of the instances must meet the flat bars (normwise and element-wise on u*
+    and the gradients, replayed patterns valid); each remaining one is held
+    to the bars scaled by s_b / 1e-5, s_b being that measured sensitivity,
+    i.e. to at most ten times the oracle's own response to the noise.  The
+    count beyond the flat bars is printed."""
     d = W.make(3)
     g = run_gpu(d, lpt=True)
-    idx = np.arange(0, d["B"], d["B"] // 256)[:256]
-    o = oracle_replay(d, g, idx=idx)
-    eu = rel(g["u"][idx], o["replay"]["u"])
-    eg = np.max([rel(g[k][idx], o["bwd"][k]) for k in ("dQ", "dp", "dx0")], axis=0)
-    s = oracle_sensitivity(d, o, idx=idx)
-    scale = np.maximum(1.0, s / 1e-6)
+    o = oracle_replay(d, g)
+    e = parity_errors(g, o)
+    flat = within_bars(e)
+    bad = np.nonzero(~flat)[0]
+    s = np.zeros(d["B"])
+    if len(bad):
+        s[bad] = oracle_sensitivity(d, o, idx=bad, orows=bad)
+    scale = np.maximum(1.0, s / 1e-5)
     iters = (g["status"] >> 8) & 255
     conv = (g["status"] & 1) != 0
-    print("cfg3 B=8192: u* max %.2e p99 %.2e | grads max %.2e | within the unscaled bars %d/%d | "
-          "oracle sensitivity max %.1e (%d above 1e-6) | converged %.3f, mean iterations %.2f"
-          % (eu.max(), np.percentile(eu, 99), eg.max(), np.sum((eu <= 1e-4) & (eg <= 1e-3)), len(idx), s.max(),
-             np.sum(s > 1e-6), conv.mean(), iters.mean()), flush=True)
-    assert np.all(eu <= 1e-4 * scale) and np.all(eg <= 1e-3 * scale)
-    assert np.mean((eu <= 1e-4) & (eg <= 1e-3)) >= 0.99
+    agree = decision_agreement(g, o)
+    print("cfg3 B=8192 (all): %s | beyond the flat bars %d/%d: %s | their oracle sensitivity %s | "
+          "decisions agree %.4f | converged %.3f, mean iterations %.2f"
+          % (describe(e), len(bad), d["B"], ["%d: u %.1e g %.1e" % (b, e["u"][b], e["g"][b]) for b in bad[:12]],
+             np.array2string(s[bad[:12]], precision=1), agree, conv.mean(), iters.mean()), flush=True)
+    assert np.mean(flat) >= 0.99
+    assert np.all(within_bars(e, scale))
+    assert alpha_choices_valid(o) == 0
     assert np.all(iters <= 10) and np.all(iters >= 1)
     # every instance either converged or hit the cap
     assert np.all((g["status"] & 3) != 0)
@@ -228,22 +238,20 @@ def test_long_horizon_parity():
     d["grad_u"] = np.random.default_rng(7).standard_normal((256, d["T_max"], 4)).astype(np.float32)
     g = run_gpu(d, K=3, tol=0.0)
     o = oracle_replay(d, g)
-    eu = rel(g["u"], o["replay"]["u"])
-    eg = np.max([rel(g[k], o["bwd"][k]) for k in ("dQ", "dp", "dx0")], axis=0)
-    print("T=50 K=3: u* max %.2e p99 %.2e | grads max %.2e" % (eu.max(), np.percentile(eu, 99), eg.max()), flush=True)
-    assert eu.max() <= 1e-4 and eg.max() <= 1e-3
+    e = parity_errors(g, o)
+    print("T=50 K=3: %s | u* p99 %.2e" % (describe(e), np.percentile(e["u"], 99)), flush=True)
+    assert np.all(within_bars(e)), describe(e)
 
 
-def test_cfg4_full_size_dense_sampled():
+def test_cfg4_full_size_dense_all_instances():
     d = W.make(4)
     assert d["ckpt"] == 10
     g = run_gpu(d, lpt=False, dlog=True, ckpt=d["ckpt"])
-    idx = np.arange(0, d["B"], d["B"] // 32)[:32]
-    o = oracle_replay(d, g, idx=idx)
-    eu = rel(g["u"][idx], o["replay"]["u"])
-    eg = max(rel(g[k][idx], o["bwd"][k]).max() for k in ("dQ", "dp", "dx0"))
-    print("cfg4 B=16384 T=50 dense: u* max %.2e grads max %.2e" % (eu.max(), eg), flush=True)
-    assert eu.max() <= 1e-4 and eg <= 1e-3
+    o = oracle_replay(d, g, free=False)
+    e = parity_errors(g, o)
+    print("cfg4 B=16384 T=50 dense (all): %s" % describe(e), flush=True)
+    assert np.all(within_bars(e)), describe(e)
+    assert alpha_choices_valid(o) == 0
     assert np.all(np.isfinite(g["u"])) and np.all(np.isfinite(g["dQ"]))
 
 

@@ -13,27 +13,23 @@ import pytest
 
 import workloads as W
 
-from gpu_util import alpha_choices_valid, decision_agreement, oracle_replay, rel, run_gpu
+from gpu_util import (TOL_G, TOL_U, alpha_choices_valid, decision_agreement, describe, oracle_replay,
+                      parity_errors, rel, run_gpu, within_bars)
 
 pytestmark = pytest.mark.gpu
-
-TOL_U, TOL_G = 1e-4, 1e-3
 
 
 def check_parity(d, g, o, label, check_grad=True):
     T = d["T"]
-    eu = rel(g["u"], o["replay"]["u"])
+    e = parity_errors(g, o)
+    if not check_grad:
+        e.pop("g", None), e.pop("g_abs", None)
     ex = rel(g["x"], o["replay"]["x"])
-    msg = "%s: u* max %.2e p99 %.2e | x* max %.2e" % (label, eu.max(), np.percentile(eu, 99), ex.max())
-    if check_grad and "bwd" in o:
-        eQ, ep, e0 = rel(g["dQ"], o["bwd"]["dQ"]), rel(g["dp"], o["bwd"]["dp"]), rel(g["dx0"], o["bwd"]["dx0"])
-        msg += " | dQ %.2e dp %.2e dx0 %.2e" % (eQ.max(), ep.max(), e0.max())
     agree = decision_agreement(g, o)
-    msg += " | decisions agree %.4f" % agree
+    msg = "%s: %s | u* p99 %.2e | x* max %.2e | decisions agree %.4f" % (
+        label, describe(e), np.percentile(e["u"], 99), ex.max(), agree)
     print(msg, flush=True)
-    assert eu.max() <= TOL_U, msg
-    if check_grad and "bwd" in o:
-        assert eQ.max() <= TOL_G and ep.max() <= TOL_G and e0.max() <= TOL_G, msg
+    assert np.all(within_bars(e)), msg
     assert alpha_choices_valid(o) == 0
     # controls inside the box, padding zero
     lo, hi = d["lo"][:, None, :], d["hi"][:, None, :]
@@ -80,7 +76,7 @@ def test_cfg1_parity_full_size():
     g = run_gpu(d, need_grad=False)
     o = oracle_replay(d, g)
     agree = check_parity(d, g, o, "cfg1 B=1024 T=20", check_grad=False)
-    assert agree >= 0.9
+    assert agree >= 0.999
 
 
 def test_persistent_equals_plain():
@@ -129,7 +125,10 @@ def test_fp64_pivot_flag_and_tiny_control_weight():
     the results are bitwise the same for every threshold, a threshold above
     every pivot flags every instance and a non-positive one flags none.
     Parity with the oracle at the conditioning-scaled bars (R = 1e-8 makes
-    the stage QPs far more ill-conditioned than the workloads)."""
+    the stage QPs far more ill-conditioned than the workloads): an instance
+    beyond the flat bars is held to them times s_b / 1e-5, where s_b is the
+    FP64 oracle's own response to input noise at FP32 resolution (1e-7), so at
+    most a hundred times the response."""
     from gpu_util import oracle_sensitivity
     d = W.make(0, B=64, r_scale=1e-6, seed=2006)
     a = run_gpu(d, fp64_pivot=1e-6)
@@ -140,10 +139,13 @@ def test_fp64_pivot_flag_and_tiny_control_weight():
     for k in ("u", "x", "dQ", "dp", "dx0", "dlog"):
         assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
     o = oracle_replay(d, a)
-    eu = rel(a["u"], o["replay"]["u"])
-    eg = np.max([rel(a[k], o["bwd"][k]) for k in ("dQ", "dp", "dx0")], axis=0)
-    s = oracle_sensitivity(d, o)
-    scale = np.maximum(1.0, s / 1e-6)
-    print("R=1e-8: flagged at 1e-6 %d/64 | u* max %.2e grads max %.2e | sensitivity max %.1e"
-          % (np.sum((a["status"] & 0x8) != 0), eu.max(), eg.max(), s.max()), flush=True)
-    assert np.all(eu <= TOL_U * scale) and np.all(eg <= TOL_G * scale)
+    e = parity_errors(a, o)
+    flat = within_bars(e)
+    s = np.zeros(d["B"])
+    if not flat.all():
+        bad = np.nonzero(~flat)[0]
+        s[bad] = oracle_sensitivity(d, o, idx=bad, orows=bad)
+    scale = np.maximum(1.0, s / 1e-5)
+    print("R=1e-8: flagged at 1e-6 %d/64 | %s | beyond the flat bars %d/64, their sensitivity max %.1e"
+          % (np.sum((a["status"] & 0x8) != 0), describe(e), np.sum(~flat), s.max()), flush=True)
+    assert np.all(within_bars(e, scale))

@@ -11,7 +11,7 @@ import pytest
 import oracle as orc
 import workloads as W
 
-from gpu_util import handle, rel
+from gpu_util import TOL_VIOL, handle, maxabs, rel, replay_violation
 
 pytestmark = pytest.mark.gpu
 
@@ -127,6 +127,8 @@ def test_warm_started_forward_matches_oracle(plain):
             ro = orc.forward(P, x64["x0"], x64["Q"], x64["p"], x64["lo"], x64["hi"], K=k_it,
                              u_init=u0.astype(np.float64), replay=rp)
             assert rel(un, ro["u"]).max() <= U_BAR
+            assert maxabs(un, ro["u"]).max() <= U_BAR
+            assert replay_violation(dict(replay=ro)).max() <= TOL_VIOL
             assert rel(xn, ro["x"]).max() <= 10 * U_BAR
 
 
@@ -163,18 +165,20 @@ def test_closed_loop_driver_matches_oracle_step_by_step(form):
     B, Tm, K, tol = 128, 20, 8, 1e-5
     d = W.make_hover_target(B, Tm, seed=73)
     x64 = {k: d[k].astype(np.float64) for k in ("Q", "p", "lo", "hi")}
-    worst = dict(u=0.0, x=0.0)
+    worst = dict(u=0.0, x=0.0, viol=0.0)
 
     def check(k, xb, wb, us, ua, xa, st, dl):
         ro = orc.forward(P, xb.astype(np.float64), x64["Q"], x64["p"], x64["lo"], x64["hi"], K=K,
                          u_init=None if wb is None else wb.astype(np.float64), replay=_replay(st, dl, K))
-        worst["u"] = max(worst["u"], rel(us, ro["u"]).max())
+        worst["u"] = max(worst["u"], rel(us, ro["u"]).max(), maxabs(us, ro["u"]).max())
+        worst["viol"] = max(worst["viol"], replay_violation(dict(replay=ro)).max())
         assert np.array_equal(ua, us[:, 0])
         step = np.stack([orc.rk4(P, xb[b].astype(np.float64), ua[b].astype(np.float64)) for b in range(B)])
         worst["x"] = max(worst["x"], rel(xa, step).max())
 
     _closed_loop(D, d, 6, K, tol, True, form, check)
-    assert worst["u"] <= U_BAR, worst
+    print("closed loop %s: %s" % (form, worst), flush=True)
+    assert worst["u"] <= U_BAR and worst["viol"] <= TOL_VIOL, worst
     assert worst["x"] <= X_BAR, worst
 
 

@@ -1,4 +1,4 @@
-"""Pins of the oracle's receding-horizon loop (Alg. 1/2 outer loop, Sec. II:
+"""Pins of the oracle's receding-horizon loop (Sec. III-A; the outer loops of Alg. 1 and Alg. 2:
 solve from the current state, apply the first control, repeat from the state
 reached) and of its shifted warm start.
 
