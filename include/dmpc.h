@@ -34,6 +34,9 @@
  *  - Calls are asynchronous on `stream` (a hipStream_t passed as void*), never
  *    synchronise the host and never allocate, so a caller may capture them in a
  *    HIP graph.  A handle is bound to one device and is not thread-safe.
+ *    An entry point that launches work makes the handle's device current for
+ *    the call and gives the calling thread its previous device back before it
+ *    returns; handles on several devices may live in one process.
  *  - Return value: DMPC_OK or a negative DMPC_E* code; dmpc_last_error() gives
  *    the message.  Numerical trouble is never an error return: it is reported
  *    per instance in `status`.

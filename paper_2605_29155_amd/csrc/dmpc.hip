@@ -1483,8 +1483,24 @@ __global__ __launch_bounds__(64) void k_tpar_tail(KArgs A, int src) {
 // backward: Riccati adjoint at (x*, u*) with the forward's active set
 // ---------------------------------------------------------------------------
 
-__constant__ uint8_t c_pk_i[NPK];
-__constant__ uint8_t c_pk_j[NPK];
+// (i, j) of packed-upper entry m, row by row.  Initialised in the code
+// object itself, so every device the library runs on holds its own copy from
+// load time on, with nothing to upload.
+struct PackTable {
+  uint8_t i[NPK], j[NPK];
+};
+constexpr PackTable make_pack_table() {
+  PackTable t{};
+  int m = 0;
+  for (int i = 0; i < NZ; ++i)
+    for (int j = i; j < NZ; ++j) {
+      t.i[m] = (uint8_t)i;
+      t.j[m] = (uint8_t)j;
+      ++m;
+    }
+  return t;
+}
+__constant__ PackTable c_pk = make_pack_table();
 
 // The stage factors (F_t, K_t, masked inverse) come from the forward's tail.
 // With checkpointing (CKPT) only V, v at the stages j * ckpt were kept: the
@@ -1688,7 +1704,7 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
       A.gQ[srow * NZ + 16] = zt[16] * zr[16];
     } else {
       for (int m = l; m < NPK; m += 16) {
-        const int i = c_pk_i[m], j = c_pk_j[m];
+        const int i = c_pk.i[m], j = c_pk.j[m];
         A.gQ[srow * NPK + m] = (i == j) ? zt[i] * zr[i] : zt[i] * zr[j] + zt[j] * zr[i];
       }
     }
@@ -1911,25 +1927,29 @@ int hip_check(dmpc_handle h, hipError_t e, const char* what) {
   return fail(h, DMPC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-bool pk_ready = false;
-
-int upload_pack_tables(dmpc_handle h) {
-  if (pk_ready) return DMPC_OK;
-  uint8_t pi[NPK], pj[NPK];
-  int m = 0;
-  for (int i = 0; i < NZ; ++i)
-    for (int j = i; j < NZ; ++j) {
-      pi[m] = (uint8_t)i;
-      pj[m] = (uint8_t)j;
-      ++m;
+// Makes a handle's device current for the life of the object and gives the
+// calling thread its previous device back afterwards.
+class DeviceScope {
+ public:
+  explicit DeviceScope(int device) {
+    err_ = hipGetDevice(&prev_);
+    if (err_ == hipSuccess && prev_ != device) {
+      err_ = hipSetDevice(device);
+      switched_ = err_ == hipSuccess;
     }
-  int rc = hip_check(h, hipMemcpyToSymbol(HIP_SYMBOL(c_pk_i), pi, sizeof pi), "pack table");
-  if (rc) return rc;
-  rc = hip_check(h, hipMemcpyToSymbol(HIP_SYMBOL(c_pk_j), pj, sizeof pj), "pack table");
-  if (rc) return rc;
-  pk_ready = true;
-  return DMPC_OK;
-}
+  }
+  ~DeviceScope() {
+    if (switched_) (void)hipSetDevice(prev_);
+  }
+  DeviceScope(const DeviceScope&) = delete;
+  DeviceScope& operator=(const DeviceScope&) = delete;
+  hipError_t status() const { return err_; }
+
+ private:
+  int prev_ = 0;
+  bool switched_ = false;
+  hipError_t err_ = hipSuccess;
+};
 
 KArgs base_args(const dmpc_config* c, void* workspace) {
   KArgs A;
@@ -1993,8 +2013,6 @@ int forward_args(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, co
   const Layout L = make_layout(cfg);
   if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace & 255))
     return fail(h, DMPC_EWORKSPACE, "workspace missing, misaligned or smaller than dmpc_workspace_bytes()");
-  rc = hip_check(h, hipSetDevice(h->device), "hipSetDevice");
-  if (rc) return rc;
   A = base_args(cfg, workspace);
   A.P = make_dyn(dyn);
   A.x0 = x0;
@@ -2125,7 +2143,12 @@ int dmpc_create(dmpc_handle* out, int device) {
     return rc;
   }
   h->cu = prop.multiProcessorCount;
-  (void)hipSetDevice(device);
+  DeviceScope scope(device);
+  rc = hip_check(h, scope.status(), "hipSetDevice");
+  if (rc) {
+    delete h;
+    return rc;
+  }
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fwd_persistent<false, 1>, 64, 0) == hipSuccess && occ > 0)
     h->occ[0][0] = occ;
@@ -2135,11 +2158,6 @@ int dmpc_create(dmpc_handle* out, int device) {
     h->occ[0][1] = occ;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fwd_persistent<true, 2>, 64, 0) == hipSuccess && occ > 0)
     h->occ[1][1] = occ;
-  rc = upload_pack_tables(h);
-  if (rc) {
-    delete h;
-    return rc;
-  }
   *out = h;
   return DMPC_OK;
 }
@@ -2161,6 +2179,9 @@ int dmpc_forward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, co
   int rc = forward_args(h, cfg, dyn, x0, Q, p, u_lo, u_hi, T, u_init, u_out, x_out, status, workspace,
                         workspace_bytes, decision_log, A);
   if (rc || cfg->B == 0) return rc;
+  DeviceScope scope(h->device);
+  rc = hip_check(h, scope.status(), "hipSetDevice");
+  if (rc) return rc;
   dmpc_launch_choice c = default_choice(cfg);
   if (cfg->flags & DMPC_TUNED) {
     auto it = h->tuned.find(shape_key(cfg, T != nullptr));
@@ -2176,6 +2197,9 @@ int dmpc_autotune(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, c
   KArgs A;
   int rc = forward_args(h, cfg, dyn, x0, Q, p, u_lo, u_hi, T, u_init, u_out, x_out, status, workspace,
                         workspace_bytes, nullptr, A);
+  if (rc) return rc;
+  DeviceScope scope(h->device);
+  rc = hip_check(h, scope.status(), "hipSetDevice");
   if (rc) return rc;
   dmpc_launch_choice best = default_choice(cfg);
   best.ms = 0.f;
@@ -2277,7 +2301,8 @@ int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, c
   const Layout L = make_layout(cfg);
   if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace & 255))
     return fail(h, DMPC_EWORKSPACE, "workspace missing, misaligned or smaller than dmpc_workspace_bytes()");
-  rc = hip_check(h, hipSetDevice(h->device), "hipSetDevice");
+  DeviceScope scope(h->device);
+  rc = hip_check(h, scope.status(), "hipSetDevice");
   if (rc) return rc;
   KArgs A = base_args(cfg, (void*)workspace);
   A.gu = grad_u;
@@ -2328,7 +2353,8 @@ int dmpc_mpc_step(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, c
   if (!x_state || !u_star) return fail(h, DMPC_EINVAL, "NULL required pointer");
   if (!(dyn.mass > 0.f) || !(dyn.Jxx > 0.f) || !(dyn.Jyy > 0.f) || !(dyn.Jzz > 0.f) || !(dyn.dt > 0.f))
     return fail(h, DMPC_EINVAL, "non-positive mass, inertia or step");
-  rc = hip_check(h, hipSetDevice(h->device), "hipSetDevice");
+  DeviceScope scope(h->device);
+  rc = hip_check(h, scope.status(), "hipSetDevice");
   if (rc) return rc;
   k_mpc_step<<<cfg->B, 64, 0, (hipStream_t)stream>>>(make_dyn(dyn), cfg->B, cfg->T_max, T, x_state, u_star, u_warm,
                                                        u_applied);
