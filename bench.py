@@ -28,8 +28,11 @@ sys.path.insert(0, ROOT)
 # box-QP, four-candidate line search; forward tail (linearise + fixed-mask
 # Riccati at the solution); adjoint sweeps; initial rollout.
 FLOP = dict(iter_stage=(27416, 30204), tail=(23478, 23478), adjoint=(1200, 2500), init=(593, 593))
-PEAK_ALU = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz, unpacked FP32 FMA = FP64 FMA rate
-PEAK_FP32_PACKED = 157.3e12
+# MI355X vector peaks (256 CU x 4 SIMD x 16 lanes x 2 FLOP per FMA x 2.4 GHz = 78.6 TFLOP/s per FMA lane
+# op): the published FP32 figure, 157.3 TFLOP/s, counts packed FP32 (two FMAs per lane op); unpacked FP32
+# and FP64 FMAs issue at 78.6 TFLOP/s.  The headline fraction is against the published FP32 peak.
+PEAK_FP32 = 157.3e12
+PEAK_UNPACKED = 78.6e12
 HBM_PEAK = 8.0e12
 
 
@@ -73,7 +76,32 @@ def make_inputs(dev, B=None):
     return d, t
 
 
-def run_gpu_bench(d, t, steps, warmup):
+def event_times(run, s, n):
+    """HIP-event time (ms) of each of n calls of run() on stream s."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for e0, e1 in ev:
+        e0.record(s)
+        run()
+        e1.record(s)
+    s.synchronize()
+    return [e0.elapsed_time(e1) for e0, e1 in ev]
+
+
+def pct(v):
+    """median, p10, p90 of a list of times."""
+    import numpy as np
+    v = np.asarray(v, np.float64)
+    return dict(median=float(np.median(v)), p10=float(np.percentile(v, 10)), p90=float(np.percentile(v, 90)), n=len(v))
+
+
+def run_gpu_bench(d, t, steps, warmup, replays=100):
+    """Times the fwd+bwd step of the tuned persistent form (captured in a HIP
+    graph: the headline) and of the per-launch form (eager, and captured in a
+    graph too), all on the same inputs.  Per form: wall-clock mean over
+    `steps` steps after `warmup` (the headline's timed region), HIP-event
+    median / p10 / p90 over `replays` single steps, the forward call's own
+    HIP-event time, and the outputs of the last step."""
     import torch
 
     import paper_2605_29155_amd as D
@@ -83,9 +111,11 @@ def run_gpu_bench(d, t, steps, warmup):
     h = D.Handle(0)
     params = D.quad_params(W.quad_params_f32())
     out = {}
-    for form in ("persistent", "plain"):
-        # the headline form uses the launch the autotuner picks for this shape
+    for form in ("persistent", "plain", "fp64"):
+        # the headline form uses the launch the autotuner picks for this shape;
+        # "fp64" is the FP64 form (DMPC_F64), tuned the same way
         flags = D.NEED_GRAD | (D.PLAIN if form == "plain" else D.LPT | D.TUNED)
+        flags |= D.F64 if form == "fp64" else 0
         cfg = D.make_config(B, Tm, D.COST_DIAG, K, 0.0, flags)
         ws = D.alloc_workspace(cfg, dev)
         u = torch.empty(B, Tm, 4, device=dev)
@@ -94,54 +124,103 @@ def run_gpu_bench(d, t, steps, warmup):
         gQ, gp, gx0 = torch.empty_like(t["Q"]), torch.empty_like(t["p"]), torch.empty_like(t["x0"])
         s = torch.cuda.Stream()
 
-        def step():
+        def fwd():
             D.forward_raw(h, cfg, params, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], None, u, x, st, ws, None, s)
+
+        def step():
+            fwd()
             D.backward_raw(h, cfg, params, None, None, None, None, ws, t["grad_u"], None, gQ, gp, gx0, s)
 
         choice = None
-        if form == "persistent":
+        if form != "plain":
             with torch.cuda.stream(s):
                 choice = D.autotune(h, cfg, params, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], None, u, x, st, ws,
                                     s).as_dict()
         with torch.cuda.stream(s):
             step()
         torch.cuda.synchronize()
-        launches = None
-        if form == "persistent":
-            # graph of the whole fwd+bwd step
-            D.capture_begin(h, s)
-            step()
-            g = D.capture_end(h, s)
-            run = lambda: D.graph_launch(h, g, s)  # noqa: E731
-        else:
-            D.forward_raw(h, cfg, params, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], None, u, x, st, ws, None, s)
-            launches = h.launch_count() + 1
-            run = step
+        fwd()
+        launches = h.launch_count() + 1
+        # graph of the whole fwd+bwd step
+        D.capture_begin(h, s)
+        step()
+        g = D.capture_end(h, s)
+        graph = lambda: D.graph_launch(h, g, s)  # noqa: E731
+        timed = graph if form != "plain" else step
         for _ in range(warmup):
-            run()
+            timed()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            run()
+            timed()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
-        # dominant kernel: the forward, timed by HIP events on its own stream
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        fwd_ms = []
-        for _ in range(max(3, min(steps, 10))):
-            e0.record(s)
-            D.forward_raw(h, cfg, params, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], None, u, x, st, ws, None, s)
-            e1.record(s)
-            D.backward_raw(h, cfg, params, None, None, None, None, ws, t["grad_u"], None, gQ, gp, gx0, s)
-            e1.synchronize()
-            fwd_ms.append(e0.elapsed_time(e1))
+        for _ in range(10):
+            graph()
+        ev_graph = pct(event_times(graph, s, replays))
+        for _ in range(10):
+            step()
+        ev_eager = pct(event_times(step, s, replays))
+        # dominant kernel: the forward call (queue reset + the forward kernel in
+        # the persistent form), HIP events on the stream it is launched on
+        ev_fwd = pct(event_times(fwd, s, 20))
+        graph()
         torch.cuda.synchronize()
-        out[form] = dict(s_per_step=dt, fwd_ms=sorted(fwd_ms)[len(fwd_ms) // 2], launches=launches, choice=choice,
+        out[form] = dict(s_per_step=dt, graph_step_ms=ev_graph, eager_step_ms=ev_eager, fwd_ms=ev_fwd["median"],
+                         fwd_ms_events=ev_fwd, launches=launches, choice=choice,
                          u=u.cpu().numpy(), x=x.cpu().numpy(), status=st.cpu().numpy().astype("uint32"),
                          dQ=gQ.cpu().numpy(), dp=gp.cpu().numpy(), dx0=gx0.cpu().numpy())
-        if form == "persistent":
-            D.graph_destroy(h, g)
+        D.graph_destroy(h, g)
     return out
+
+
+def torch_steps(d, t, steps=20, warmup=3):
+    """The layer as a torch module user calls it: DMPCLayer (the module-level
+    autograd.Function, autotuned) on the same inputs, loss sum_b u*_b,0 . w_b,
+    loss.backward().  layer_ms: x0, Q, p given as leaf tensors; full_ms: the
+    cost MLP on the GPU emits Q, p (forward and backward through it too).
+    Wall-clock mean per step, stream synchronised."""
+    import numpy as np
+    import torch
+
+    import paper_2605_29155_amd as D
+    import workloads as W
+    dev = t["x0"].device
+    layer = D.DMPCLayer(W.quad_params_f32(), max_iter=d["K"], autotune=True)
+    w = torch.from_numpy(d["w"]).to(dev)
+    x0 = t["x0"].clone().requires_grad_(True)
+    Q = t["Q"].clone().requires_grad_(True)
+    p = t["p"].clone().requires_grad_(True)
+    mlp = W.CostMLP(d["T_max"], W.CONFIGS[2]["seed"], device=dev)
+    inp = torch.from_numpy(np.ascontiguousarray(d["mlp_input"])).to(dev)
+
+    def layer_step():
+        for a in (x0, Q, p):
+            a.grad = None
+        u, _, _ = layer(x0, Q, p, t["lo"], t["hi"])
+        (u[:, 0, :] * w).sum().backward()
+
+    def full_step():
+        for a in mlp.params:
+            a.grad = None
+        Qm, pm = mlp(inp)
+        u, _, _ = layer(t["x0"], Qm, pm, t["lo"], t["hi"])
+        (u[:, 0, :] * w).sum().backward()
+
+    res = {}
+    for name, fn in (("layer_ms", layer_step), ("full_ms", full_step)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / steps * 1e3
+    # the layer's gradients equal the raw C ABI's on the same inputs
+    layer_step()
+    res["dp_layer"] = p.grad.cpu().numpy()
+    return res
 
 
 def profile_short(d, t):
@@ -300,49 +379,252 @@ def closed_loop_latency(steps=40, warmup=5):
     return rows
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline_leg(d, gpu, nsample=64):
-    """Oracle on the host: time fwd + Riccati-adjoint bwd of the full batch on
-    all host cores, and check the kernel on a sample with its decisions
-    replayed (needs the decision log: one extra kernel run)."""
+    """The FP64 oracle on the host (never tuned; test infrastructure):
+    - forward + Riccati-adjoint backward of the full batch on the host threads
+      this process may use (at most 16), repeated for about 10 s;
+    - the same on one thread, on the first 256 instances, scaled to solves/s;
+    - the dense-KKT backward (the verification path) on 256 instances with
+      all threads, its time per solve scaled linearly to the batch;
+    and checks the kernel on a sample with its decisions replayed (one extra
+    kernel run with the decision log): errors, decision agreement with a free
+    oracle run, the fraction of controls on a bound, the iteration counts."""
     import numpy as np
     import torch
 
     import oracle as orc
-    import paper_2605_29155_amd as D
     import workloads as W
     sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from gpu_util import oracle_replay, rel, run_gpu
+    from gpu_util import decision_agreement, maxabs, oracle_replay, rel, replay_violation, run_gpu
     P = orc.params_from(W.quad_params_f32())
-    nthreads = min(16, os.cpu_count() or 1)
-    # repeat the full batch until about 10 s of wall time have been spent
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    nthreads = max(1, min(16, avail))
+
+    def fwd_bwd(sl, nt):
+        a = {k: d[k][sl] for k in ("x0", "Q", "p", "lo", "hi", "T", "grad_u")}
+        f = orc.forward(P, a["x0"], a["Q"], a["p"], a["lo"], a["hi"], a["T"], K=d["K"], nthreads=nt)
+        orc.backward(P, a["x0"], a["Q"], a["p"], a["lo"], a["hi"], f["u"], f["x"], a["grad_u"], T=a["T"],
+                     nthreads=nt)
+        return f
+
+    def repeat(fn, budget):
+        t0, reps = time.perf_counter(), 0
+        while True:
+            fn()
+            reps += 1
+            wall = time.perf_counter() - t0
+            if wall >= budget or reps >= 60:
+                return reps, wall
+
+    full = slice(None)
+    reps, wall = repeat(lambda: fwd_bwd(full, nthreads), 10.0)
+    n1 = min(256, d["B"])
+    reps1, wall1 = repeat(lambda: fwd_bwd(slice(0, n1), 1), 3.0)
+    f = fwd_bwd(slice(0, n1), nthreads)
+    a = {k: d[k][:n1] for k in ("x0", "Q", "p", "lo", "hi", "T", "grad_u")}
     t0 = time.perf_counter()
-    reps = 0
-    while True:
-        f = orc.forward(P, d["x0"], d["Q"], d["p"], d["lo"], d["hi"], d["T"], K=d["K"], nthreads=nthreads)
-        orc.backward(P, d["x0"], d["Q"], d["p"], d["lo"], d["hi"], f["u"], f["x"], d["grad_u"], T=d["T"],
-                     nthreads=nthreads)
-        reps += 1
-        wall = time.perf_counter() - t0
-        if wall >= 10.0 or reps >= 60:
-            break
+    orc.backward(P, a["x0"], a["Q"], a["p"], a["lo"], a["hi"], f["u"], f["x"], a["grad_u"], T=a["T"], method=1,
+                 nthreads=nthreads)
+    kkt_s = time.perf_counter() - t0
     cpu = dict(value=reps * d["B"] / wall, unit="solves/s", cores=nthreads, kind="oracle",
                sample="full batch B=%d T=%d K=%d repeated %d times, FP64 forward + Riccati-adjoint backward, "
-                      "%.1f s wall" % (d["B"], d["T_max"], d["K"], reps, wall))
+                      "%d threads, %.1f s wall" % (d["B"], d["T_max"], d["K"], reps, nthreads, wall),
+               host_cpu=cpu_model(), host_nproc=os.cpu_count(), threads_available=avail,
+               single_thread=dict(value=reps1 * n1 / wall1, unit="solves/s",
+                                  sample="first %d instances repeated %d times on 1 thread, %.1f s wall"
+                                         % (n1, reps1, wall1)),
+               dense_kkt_backward=dict(ms_per_solve=kkt_s / n1 * 1e3, batch_s_scaled=kkt_s / n1 * d["B"],
+                                       sample="%d instances, %d threads, %.2f s wall; scaled linearly to B=%d "
+                                              "(instances are independent)" % (n1, nthreads, kkt_s, d["B"])))
     # accuracy on a sample, decisions replayed
     idx = np.arange(0, d["B"], d["B"] // nsample)[:nsample]
     g = run_gpu(d, lpt=True)
     o = oracle_replay(d, g, idx=idx)
-    sel = lambda a: a[idx]  # noqa: E731
+    sel = lambda v: v[idx]  # noqa: E731
     acc = dict(sample=len(idx),
                u_rel_max=float(rel(sel(g["u"]), o["replay"]["u"]).max()),
+               u_abs_max=float(maxabs(sel(g["u"]), o["replay"]["u"]).max()),
                dQ_rel_max=float(rel(sel(g["dQ"]), o["bwd"]["dQ"]).max()),
                dp_rel_max=float(rel(sel(g["dp"]), o["bwd"]["dp"]).max()),
-               dx0_rel_max=float(rel(sel(g["dx0"]), o["bwd"]["dx0"]).max()))
+               dx0_rel_max=float(rel(sel(g["dx0"]), o["bwd"]["dx0"]).max()),
+               grad_abs_max=float(max(maxabs(sel(g[k]), o["bwd"][k]).max() for k in ("dQ", "dp", "dx0"))),
+               replayed_pattern_violation_max=float(replay_violation(o).max()),
+               decision_agreement=float(decision_agreement(g, o, idx)))
     # the timed persistent run and the decision-logged run must agree exactly
     acc["bench_run_matches_logged_run"] = bool(np.array_equal(gpu["persistent"]["u"], g["u"]))
+    u = gpu["persistent"]["u"]
+    lo, hi = d["lo"][:, None, :], d["hi"][:, None, :]
+    acc["active_fraction"] = float(np.mean((u <= lo) | (u >= hi)))
+    its = (gpu["persistent"]["status"] >> 8) & 255
+    acc["iterations_histogram"] = {int(k): int(v) for k, v in zip(*np.unique(its, return_counts=True))}
     torch.cuda.synchronize()
-    del D
     return cpu, acc
+
+
+def _tensors(d, dev):
+    import numpy as np
+    import torch
+    t = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev) for k in ("x0", "Q", "p", "lo", "hi", "grad_u")}
+    t["T"] = torch.from_numpy(d["T"].astype(np.int32)).to(dev)
+    return t
+
+
+def _solver(h, d, t, flags, dev):
+    """fwd / step closures of one launch form on workload d (horizons given)."""
+    import torch
+
+    import paper_2605_29155_amd as D
+    import workloads as W
+    B, Tm = d["B"], d["T_max"]
+    cfg = D.make_config(B, Tm, d["cost_kind"], d["K"], d["tol"], flags, 1e-6, d["ckpt"])
+    ws = D.alloc_workspace(cfg, dev)
+    par = D.quad_params(W.quad_params_f32())
+    o = dict(u=torch.empty(B, Tm, 4, device=dev), x=torch.empty(B, Tm, 13, device=dev),
+             st=torch.empty(B, dtype=torch.int32, device=dev), gQ=torch.empty_like(t["Q"]),
+             gp=torch.empty_like(t["p"]), gx0=torch.empty_like(t["x0"]))
+    s = torch.cuda.Stream()
+
+    def fwd():
+        D.forward_raw(h, cfg, par, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], t["T"], o["u"], o["x"], o["st"], ws,
+                      None, s)
+
+    def step():
+        fwd()
+        D.backward_raw(h, cfg, par, t["Q"], t["p"], t["lo"], t["hi"], ws, t["grad_u"], None, o["gQ"], o["gp"],
+                       o["gx0"], s)
+
+    def tune():
+        with torch.cuda.stream(s):
+            return D.autotune(h, cfg, par, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], t["T"], o["u"], o["x"],
+                              o["st"], ws, s).as_dict()
+
+    return dict(cfg=cfg, ws=ws, out=o, s=s, fwd=fwd, step=step, tune=tune)
+
+
+def config_lines(replays=20):
+    """fwd+bwd step of the ragged workload (B=8192, T in 10..50, up to 10
+    iterations with the ||du||_inf < 1e-5 stop, bounds hi ~ U[6,10]) and of
+    the large dense one (B=16384, T=50, dense Wishart cost, checkpoints every
+    10 stages): the autotuned persistent form and the per-launch form, each
+    eager and captured in a HIP graph; HIP-event median / p10 / p90 over
+    `replays` steps.  One JSON line per workload."""
+    import numpy as np
+    import torch
+
+    import paper_2605_29155_amd as D
+    import workloads as W
+    dev = "cuda:0"
+    h = D.Handle(0)
+    lines = []
+    for cid, name in ((3, "ragged_B8192_T10-50_K10_tol1e-5"), (4, "dense_B16384_T50_K5_ckpt10")):
+        print("bench: building workload %s" % name, file=sys.stderr, flush=True)
+        d = W.make(cid)
+        t = _tensors(d, dev)
+        B = d["B"]
+        row = dict(workload=name, B=B, T_max=d["T_max"], K=d["K"], tol=d["tol"], ckpt=d["ckpt"],
+                   cost="dense" if d["cost_kind"] else "diag")
+        for form, flags in (("persistent", D.NEED_GRAD | D.LPT | D.TUNED), ("plain", D.NEED_GRAD | D.PLAIN),
+                            ("fp64", D.NEED_GRAD | D.LPT | D.TUNED | D.F64)):
+            S = _solver(h, d, t, flags, dev)
+            if form != "plain":
+                row["launch_choice" if form == "persistent" else "launch_choice_fp64"] = S["tune"]()
+            S["step"]()
+            torch.cuda.synchronize()
+            D.capture_begin(h, S["s"])
+            S["step"]()
+            g = D.capture_end(h, S["s"])
+            graph = lambda: D.graph_launch(h, g, S["s"])  # noqa: E731
+            graph()
+            ev_g = pct(event_times(graph, S["s"], replays))
+            S["step"]()
+            ev_e = pct(event_times(S["step"], S["s"], replays))
+            ev_f = pct(event_times(S["fwd"], S["s"], max(5, replays // 2)))
+            st = S["out"]["st"].cpu().numpy().astype(np.uint32)
+            its = (st >> 8) & 255
+            row[form] = dict(graph_step_ms=ev_g, eager_step_ms=ev_e, fwd_ms=ev_f,
+                             solves_per_s=B / (ev_g["median"] * 1e-3))
+            if form == "persistent":
+                Tb = d["T"].astype(np.float64)
+                i = 1 if d["cost_kind"] else 0
+                fl = Tb * (FLOP["init"][i] + its * FLOP["iter_stage"][i] + FLOP["tail"][i])
+                ach = fl.sum() / (ev_f["median"] * 1e-3)
+                row["roofline_fwd"] = dict(achieved=ach / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
+                                           frac=ach / PEAK_FP32, frac_vs_unpacked_78_6=ach / PEAK_UNPACKED,
+                                           flop_fwd_total=float(fl.sum()),
+                                           basis="per instance T_b (593 + k_b 27416 + 23478) diag / (593 + k_b "
+                                                 "30204 + 23478) dense, k_b the iterations it used")
+                row["iterations"] = dict(mean=float(its.mean()), converged=float(np.mean((st & 1) != 0)))
+            D.graph_destroy(h, g)
+            del S
+            torch.cuda.synchronize()
+        row["speedup_vs_plain_graph"] = row["plain"]["graph_step_ms"]["median"] / row["persistent"]["graph_step_ms"]["median"]
+        row["speedup_vs_plain_eager"] = row["plain"]["eager_step_ms"]["median"] / row["persistent"]["graph_step_ms"]["median"]
+        print(json.dumps(row), flush=True)
+        lines.append(row)
+    return lines
+
+
+def tune_survey():
+    """Forward time of every launch choice the autotuner considers, each
+    pinned with dmpc_set_tuned and timed with HIP events (best of three after
+    a warm-up), then dmpc_autotune's own pick, on the metric workload (B=4096,
+    T=20, MLP cost), the ragged one (B=8192, T in 10..50) and the large dense
+    one (B=16384, T=50, checkpoints).  Prints a markdown table."""
+    import torch
+
+    import paper_2605_29155_amd as D
+    import workloads as W
+    dev = "cuda:0"
+    h = D.Handle(0)
+    wl = ((2, "B=4096 T=20 diag (MLP cost)"), (3, "B=8192 T=10..50 ragged"), (4, "B=16384 T=50 dense, ckpt 10"))
+    print("| workload | form | waves/SIMD | grid | order | forward ms |")
+    print("|---|---|---|---|---|---|")
+    picks = []
+    for cid, name in wl:
+        d = W.make(cid)
+        t = _tensors(d, dev)
+        S = _solver(h, d, t, D.NEED_GRAD | D.LPT | D.TUNED, dev)
+        cands = [D.LaunchChoice(1, 0, 1, 0, 0.0)]
+        for occ in (1, 2):
+            for grid in (0, 1):
+                for lpt in (0, 1):
+                    cands.append(D.LaunchChoice(0, lpt, occ, grid, 0.0))
+        for c in cands:
+            D.set_tuned(h, S["cfg"], True, c)
+            S["fwd"]()
+            ms = min(event_times(S["fwd"], S["s"], 3))
+            if c.plain:
+                print("| %s | per-launch | - | - | - | %.3f |" % (name, ms), flush=True)
+            else:
+                print("| %s | persistent | %d | %s | %s | %.3f |"
+                      % (name, c.waves_per_simd, "one wave per unit" if c.grid_mode else "resident + queue",
+                         "longest first" if c.lpt else "queue", ms), flush=True)
+        ch = S["tune"]()
+        picks.append((name, ch))
+        del S
+        torch.cuda.synchronize()
+    print()
+    print("Choices dmpc_autotune stored:")
+    print()
+    for name, ch in picks:
+        if ch["plain"]:
+            print("- %s: per-launch form, %.3f ms" % (name, ch["ms"]))
+        else:
+            print("- %s: persistent, %d wave(s)/SIMD, %s, %s, %.3f ms"
+                  % (name, ch["waves_per_simd"], "one wave per unit" if ch["grid_mode"] else "resident + queue",
+                     "longest horizon first" if ch["lpt"] else "queue order", ch["ms"]))
+    print()
+    print("Kernel source hash %s." % kernel_source_hash(), flush=True)
 
 
 def main():
@@ -361,6 +643,12 @@ def main():
                     help="one GPU's share of the metric workload split over G GPUs (B = 4096 / G, T = 20): "
                          "fwd+bwd step time of the tuned persistent form and of the per-launch form; prints one "
                          "JSON line")
+    ap.add_argument("--configs", action="store_true",
+                    help="fwd+bwd step of the ragged (B=8192) and large dense (B=16384, T=50) workloads, tuned "
+                         "persistent and per-launch forms, eager and graph-captured; one JSON line each")
+    ap.add_argument("--tune-survey", action="store_true",
+                    help="forward time of every launch choice on the metric, ragged and dense workloads, and the "
+                         "autotuner's pick; prints a markdown table")
     ap.add_argument("--profile-short", action="store_true",
                     help="for counter collection: two direct fwd+bwd calls of the persistent form, then a "
                          "256 MiB device copy whose FETCH_SIZE / WRITE_SIZE calibrate the HBM counters")
@@ -378,6 +666,12 @@ def main():
     if a.closed_loop:
         print(json.dumps({"closed_loop_latency": closed_loop_latency(), "workload": "hover_to_random_target, B=1"}),
               flush=True)
+        return
+    if a.configs:
+        config_lines()
+        return
+    if a.tune_survey:
+        tune_survey()
         return
     if a.shard > 0:
         Bs = 4096 // a.shard
@@ -399,9 +693,9 @@ def main():
     res = run_gpu_bench(d, t, a.steps, a.warmup)
     B, T, K = d["B"], d["T_max"], d["K"]
     f_fwd, f_bwd = flops_per_solve(T, K)
-    per = res["persistent"]
+    per, pl = res["persistent"], res["plain"]
     value = B / per["s_per_step"]
-    plain_value = B / res["plain"]["s_per_step"]
+    plain_value = B / pl["s_per_step"]
     achieved = f_fwd * B / (per["fwd_ms"] * 1e-3)
     kh = kernel_source_hash()
     ch = per["choice"]
@@ -413,6 +707,9 @@ def main():
                 % (ch["waves_per_simd"], ch["grid_mode"], "longest-first" if ch["lpt"] else "queue"))
         kname = "k_fwd_persistent<false, %d>" % ch["waves_per_simd"]
         traffic = load_traffic(kh, B) if ch["waves_per_simd"] == 1 else None
+    print("bench: torch steps through DMPCLayer", file=sys.stderr, flush=True)
+    ts = torch_steps(d, t)
+    import numpy as np
     line = {
         "metric": "fwd+bwd diff-MPC solves/s @B=4096,T=20 FP32 vs plain GPU; grad rel err",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -420,12 +717,26 @@ def main():
         "dtype": "f32+f64acc", "data": "synthetic",
         "config": {"workload": "diffmpc_quadrotor_B4096_T20_K5_mlpcost", "B": B, "T": T, "K": K,
                    "cost": "diag (MLP-emitted)", "form": form, "launch_choice": ch},
-        "plain": {"value": plain_value, "ms_per_step": res["plain"]["s_per_step"] * 1e3,
-                  "launches_fwd": res["plain"]["launches"], "speedup": value / plain_value},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_ALU, "traffic": traffic,
+        "step_ms_events": {"persistent_graph": per["graph_step_ms"], "persistent_eager": per["eager_step_ms"],
+                           "plain_graph": pl["graph_step_ms"], "plain_eager": pl["eager_step_ms"]},
+        "fp64_form": {"graph_step_ms": res["fp64"]["graph_step_ms"], "fwd_ms": res["fp64"]["fwd_ms"],
+                      "value": B / (res["fp64"]["graph_step_ms"]["median"] * 1e-3),
+                      "launch_choice": res["fp64"]["choice"],
+                      "note": "DMPC_F64: dynamics, linearisation, line search and stored trajectories in FP64"},
+        "plain": {"value": plain_value, "ms_per_step": pl["s_per_step"] * 1e3, "form": "per-launch, eager",
+                  "launches_fwd": pl["launches"], "speedup": value / plain_value,
+                  "graph_value": B / (pl["graph_step_ms"]["median"] * 1e-3),
+                  "speedup_vs_plain_graph": pl["graph_step_ms"]["median"] / per["graph_step_ms"]["median"]},
+        "torch_step": {"layer_ms": ts["layer_ms"], "full_ms": ts["full_ms"],
+                       "note": "DMPCLayer (autograd.Function) fwd + loss.backward, wall clock; full_ms includes "
+                               "the cost MLP's forward and backward",
+                       "layer_grad_equals_raw": bool(np.array_equal(ts["dp_layer"], per["dp"]))},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": traffic,
                      "kernel": kname, "kernel_ms": per["fwd_ms"],
-                     "flop_per_solve_fwd": f_fwd, "frac_vs_fp32_packed": achieved / PEAK_FP32_PACKED},
+                     "kernel_ms_is": "median HIP-event time of the forward call (queue reset + forward kernel) on "
+                                     "the stream it is launched on, 20 calls after the timed region",
+                     "flop_per_solve_fwd": f_fwd, "frac_vs_unpacked_78_6": achieved / PEAK_UNPACKED},
         "kernel_source_hash": kh,
     }
     if not a.no_cpu:

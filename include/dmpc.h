@@ -83,6 +83,21 @@ extern "C" {
                                results as the serial form up to rounding; meant for small B and long
                                T, where the serial recursion in time sets the latency.  Sizes the
                                workspace for it (about 8.4 KiB more per instance-stage) */
+#define DMPC_F64 0x20u      /* FP64 form of the persistent forward: the dynamics, the linearisation,
+                               the line search and the stored trajectories and gains in double
+                               precision (the stage algebra and the control block are FP64 in both
+                               forms).  For long unconverged runs whose iterate is sensitive to
+                               FP32 rounding.  Inputs and outputs stay float32; the workspace's
+                               trajectory and gain regions double in size.  Not with DMPC_PLAIN or
+                               DMPC_TPAR (DMPC_EUNSUPPORTED) */
+#define DMPC_F64_REDO 0x40u /* FP64 path for ill-conditioned costs: after the FP32 form's forward,
+                               every instance with DMPC_ST_FP64 (a pivot of its control-block
+                               factorisation below fp64_pivot) is solved again from the start in the
+                               FP64 form and gets DMPC_ST_F64_REDONE; its outputs, decision log and
+                               backward factors are the FP64 form's.  Three more launches; the
+                               workspace grows by the FP64 form's trajectory and gain regions.  Not
+                               with DMPC_PLAIN or DMPC_TPAR (DMPC_EUNSUPPORTED) nor DMPC_F64
+                               (DMPC_EINVAL) */
 
 /* per-instance status word */
 #define DMPC_ST_CONVERGED 0x1u   /* tol_du > 0 and ||U^k - U^{k-1}||_inf < tol_du was reached */
@@ -93,6 +108,7 @@ extern "C" {
                                     L D L^T, whose pivots D_i are the squares of Cholesky's) */
 #define DMPC_ST_QPMAXITER 0x10u  /* a stagewise box-QP hit its iteration cap */
 #define DMPC_ST_REGULARIZED 0x20u /* a non-positive pivot remained; the block was shifted */
+#define DMPC_ST_F64_REDONE 0x40u /* DMPC_F64_REDO: the instance was solved again in the FP64 form */
 #define DMPC_ST_ITERS_SHIFT 8    /* bits 8..15: iLQR iterations performed */
 
 /* decision log (optional forward output): [B][max_iter][1 + T_max] bytes.
@@ -124,7 +140,8 @@ typedef struct {
                          recomputes the factors segment by segment (twice) from those checkpoints;
                          the gradients are the same.  Checkpointing for long horizons. */
   float fp64_pivot;   /* pivot threshold below which a stage sets DMPC_ST_FP64; <= 0 disables */
-  uint32_t flags;     /* DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT | DMPC_TUNED | DMPC_TPAR */
+  uint32_t flags;     /* DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT | DMPC_TUNED | DMPC_TPAR | DMPC_F64 |
+                         DMPC_F64_REDO */
 } dmpc_config;
 
 /* How a forward is launched.  None of these changes the arithmetic of the
@@ -238,6 +255,17 @@ int dmpc_get_tuned(dmpc_handle h, const dmpc_config* cfg, int has_T, dmpc_launch
 
 /* The launch choice the last dmpc_forward / dmpc_autotune on this handle used. */
 int dmpc_last_launch_choice(dmpc_handle h, dmpc_launch_choice* choice);
+
+/* Persisted launch choices, so that a shape is tuned once per machine rather
+ * than once per process.  dmpc_tuned_save writes every choice stored on the
+ * handle to the text file `path` (replacing it), one line per shape, keyed by
+ * the device's architecture name and compute-unit count; it returns the
+ * number of lines written.  dmpc_tuned_load adds the choices of such a file
+ * to the handle, skipping lines saved for another architecture or CU count
+ * and malformed ones, and returns the number taken.  DMPC_EINVAL for a NULL
+ * argument or a file that cannot be opened.  Host-only; no GPU work. */
+int dmpc_tuned_save(dmpc_handle h, const char* path);
+int dmpc_tuned_load(dmpc_handle h, const char* path);
 
 /* Graph helpers: begin capturing `stream`; enqueue dmpc_forward/dmpc_backward
  * calls; end the capture into an executable graph.  The captured work uses

@@ -17,8 +17,9 @@ from . import build as _build
 
 NX, NU, NZ, NPACK = 13, 4, 17, 153
 COST_DIAG, COST_DENSE = 0, 1
-NEED_GRAD, PLAIN, LPT, TUNED, TPAR = 0x1, 0x2, 0x4, 0x8, 0x10
+NEED_GRAD, PLAIN, LPT, TUNED, TPAR, F64, F64_REDO = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40
 ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_FP64, ST_QPMAXITER, ST_REGULARIZED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+ST_F64_REDONE = 0x40
 ITERS_SHIFT = 8
 ALPHA_NONE = 255
 ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "EHIP", -4: "EWORKSPACE"}
@@ -75,6 +76,8 @@ def lib():
         L.dmpc_set_tuned.argtypes = [vp, C.POINTER(Config), i32, C.POINTER(LaunchChoice)]
         L.dmpc_get_tuned.argtypes = [vp, C.POINTER(Config), i32, C.POINTER(LaunchChoice)]
         L.dmpc_last_launch_choice.argtypes = [vp, C.POINTER(LaunchChoice)]
+        L.dmpc_tuned_save.argtypes = [vp, C.c_char_p]
+        L.dmpc_tuned_load.argtypes = [vp, C.c_char_p]
         L.dmpc_capture_begin.argtypes = [vp, vp]
         L.dmpc_capture_end.argtypes = [vp, vp, C.POINTER(vp)]
         L.dmpc_graph_launch.argtypes = [vp, vp, vp]
@@ -188,6 +191,23 @@ def get_tuned(h, cfg, has_T):
     return None if rc != 0 else c
 
 
+def tuned_save(h, path):
+    """Write the handle's tuned launch choices to path; returns their number."""
+    n = lib().dmpc_tuned_save(h._h, os.fsencode(path))
+    if n < 0:
+        h.check(n, "dmpc_tuned_save")
+    return n
+
+
+def tuned_load(h, path):
+    """Add the choices saved in path for this device's architecture; returns
+    how many were taken."""
+    n = lib().dmpc_tuned_load(h._h, os.fsencode(path))
+    if n < 0:
+        h.check(n, "dmpc_tuned_load")
+    return n
+
+
 def last_launch_choice(h):
     c = LaunchChoice()
     h.check(lib().dmpc_last_launch_choice(h._h, C.byref(c)), "dmpc_last_launch_choice")
@@ -263,6 +283,8 @@ def _make_function():
             st = torch.empty(B, device=p.device, dtype=torch.int32)
             if layer.autotune and get_tuned(layer.handle, cfg, T is not None) is None:
                 autotune(layer.handle, cfg, params, x0, Q, p, u_lo, u_hi, T, u, x, st, ws)
+                if layer.tune_file:
+                    tuned_save(layer.handle, layer.tune_file)
             else:
                 forward_raw(layer.handle, cfg, params, x0, Q, p, u_lo, u_hi, T, u, x, st, ws)
             ctx.cfg, ctx.ws, ctx.layer, ctx.params = cfg, ws, layer, params
@@ -315,21 +337,37 @@ class DMPCLayer:
     the backward returns dL/d(dyn) (the batch sum of dL/dtheta)."""
 
     def __init__(self, params, max_iter=5, tol_du=0.0, cost_kind=COST_DIAG, plain=False, lpt=True,
-                 fp64_pivot=1e-6, ckpt_every=0, autotune=False, tpar=False, device=0):
+                 fp64_pivot=1e-6, ckpt_every=0, autotune=False, tpar=False, device=0, tune_file=None,
+                 fp64=False, fp64_redo=False):
         """autotune: on the first call for a shape, time the launch choices
         (dmpc_autotune) and use the fastest for that shape from then on.
-        tpar: per-launch form with the time-parallel Riccati (small B, long T)."""
+        tune_file: with autotune, a file of saved launch choices: read at
+        construction if it exists, rewritten after each new tuning, so a shape
+        is tuned once per machine.
+        tpar: per-launch form with the time-parallel Riccati (small B, long T).
+        fp64: the FP64 form (DMPC_F64): dynamics, linearisation, line search
+        and stored trajectories in double, for long unconverged runs whose
+        iterate is sensitive to FP32 rounding.
+        fp64_redo: the FP32 form, with the instances whose control block had
+        a pivot below fp64_pivot solved again in the FP64 form (DMPC_F64_REDO)."""
         self.handle = Handle(device)
         self.autotune = autotune
+        self.tune_file = tune_file
+        if autotune and tune_file and os.path.exists(tune_file):
+            tuned_load(self.handle, tune_file)
         self.params = quad_params(params) if isinstance(params, dict) else params
         self.max_iter, self.tol_du, self.cost_kind = max_iter, tol_du, cost_kind
         self.plain, self.lpt, self.fp64_pivot, self.ckpt_every = plain, lpt, fp64_pivot, ckpt_every
         self.tpar = tpar
+        self.fp64 = fp64
+        self.fp64_redo = fp64_redo
 
     def config(self, B, T_max, need_grad=True):
         flags = (NEED_GRAD if need_grad else 0) | (PLAIN if self.plain else 0) | (LPT if self.lpt else 0)
         flags |= TUNED if self.autotune else 0
         flags |= TPAR if self.tpar else 0
+        flags |= F64 if self.fp64 else 0
+        flags |= F64_REDO if self.fp64_redo else 0
         return make_config(B, T_max, self.cost_kind, self.max_iter, self.tol_du, flags, self.fp64_pivot,
                            self.ckpt_every)
 

@@ -18,6 +18,8 @@
 #include <vector>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <utility>
 
@@ -33,8 +35,8 @@ struct Ws {
   int* state;   // [B][SW]
   int* queue;   // work counter of the persistent launch
   int* order;   // [B] instance order (longest horizon first)
-  float* traj;  // [B][NSLOT][Tm][ZS]
-  float* gains; // [B][Tm][GS]
+  float* traj;  // [B][NSLOT][Tm][ZS] in the dynamics precision (float, or double in the FP64 form)
+  float* gains; // [B][Tm][GS] in the dynamics precision
   float* lin;   // [B][Tm][FS]  (per-launch form)
   float* tail;  // [B][tstride][TS]  stage factors for the backward: every stage,
                 //   or (checkpointing) one segment, recomputed by the backward
@@ -42,6 +44,8 @@ struct Ws {
   double* ck;   // [B][nck][CK_W] checkpoints of (V, v) at stages j * ckpt
   double* elem;  // [2][B][Tm][EL_W] time-parallel Riccati elements (ping-pong), or null
   uint8_t* pat;  // [B][Tm] clamp pattern of the last backward pass (time-parallel guess), or null
+  float* traj64;   // with DMPC_F64_REDO: the FP64 redo's trajectories [B][NSLOT][Tm][ZS] doubles, else null
+  float* gains64;  // with DMPC_F64_REDO: the FP64 redo's gains [B][Tm][GS] doubles, else null
 };
 
 struct KArgs {
@@ -62,6 +66,12 @@ struct KArgs {
   float *gQ, *gp, *gx0;
   float* gdyn;           // [B][8] dL/d(model constants) or null
   dmpc_quad_params raw;  // model constants as given (for gdyn)
+  Dyn64 P64;             // the constants of P in double (the FP64 form's dynamics)
+  // FP64 redo of flagged instances: their number (device), or null for a
+  // launch over the whole batch; the float trajectory region the redo copies
+  // its final nominal into (read by the backward)
+  const int* redo_count;
+  float* traj_f;
 };
 
 struct Grp {
@@ -75,11 +85,21 @@ __device__ __forceinline__ void mem_fence_wg() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-__device__ __forceinline__ float* traj_at(const KArgs& A, int b, int s, int t) {
-  return A.ws.traj + (((size_t)b * NSLOT + s) * A.Tm + t) * ZS;
+// the dynamics constants in precision R
+template <class R>
+__device__ __forceinline__ const DynT<R>& dyn_of(const KArgs& A);
+template <>
+__device__ __forceinline__ const DynT<float>& dyn_of<float>(const KArgs& A) { return A.P; }
+template <>
+__device__ __forceinline__ const DynT<double>& dyn_of<double>(const KArgs& A) { return A.P64; }
+
+template <class R = float>
+__device__ __forceinline__ R* traj_at(const KArgs& A, int b, int s, int t) {
+  return (R*)A.ws.traj + (((size_t)b * NSLOT + s) * A.Tm + t) * ZS;
 }
-__device__ __forceinline__ float* gains_at(const KArgs& A, int b, int t) {
-  return A.ws.gains + ((size_t)b * A.Tm + t) * GS;
+template <class R = float>
+__device__ __forceinline__ R* gains_at(const KArgs& A, int b, int t) {
+  return (R*)A.ws.gains + ((size_t)b * A.Tm + t) * GS;
 }
 __device__ __forceinline__ float* lin_at(const KArgs& A, int b, int t) { return A.ws.lin + ((size_t)b * A.Tm + t) * FS; }
 // tl: stage index within the stored range (t itself, or t - segment start)
@@ -87,7 +107,50 @@ __device__ __forceinline__ float* tail_at(const KArgs& A, int b, int tl) {
   return A.ws.tail + ((size_t)b * A.tstride + tl) * TS;
 }
 
+// four values of precision R: one 16-byte access for float, two for double
+template <class R>
+struct V4 {
+  R x, y, z, w;
+};
+__device__ __forceinline__ float4 ld4(const float* p) { return *(const float4*)p; }
+__device__ __forceinline__ V4<double> ld4(const double* p) {
+  const double2 a = *(const double2*)p, c = *(const double2*)(p + 2);
+  return {a.x, a.y, c.x, c.y};
+}
+__device__ __forceinline__ void st4(float* p, float a, float b, float c, float d) {
+  *(float4*)p = make_float4(a, b, c, d);
+}
+__device__ __forceinline__ void st4(double* p, double a, double b, double c, double d) {
+  *(double2*)p = make_double2(a, b);
+  *(double2*)(p + 2) = make_double2(c, d);
+}
+
 __device__ __forceinline__ int pidx(int i, int j) { return 17 * i - (i * (i - 1)) / 2 + (j - i); }
+
+__device__ __forceinline__ void load_z(const double* zp, double* z) {
+#pragma unroll
+  for (int i = 0; i < 12; i += 2) {
+    const double2 w = *(const double2*)(zp + i);
+    z[i] = w.x;
+    z[i + 1] = w.y;
+  }
+  z[12] = zp[12];
+#pragma unroll
+  for (int i = 0; i < 4; i += 2) {
+    const double2 w = *(const double2*)(zp + 16 + i);
+    z[13 + i] = w.x;
+    z[14 + i] = w.y;
+  }
+}
+
+__device__ __forceinline__ void store_z(double* zp, const double* x, const double* u) {
+#pragma unroll
+  for (int i = 0; i < 12; i += 2) *(double2*)(zp + i) = make_double2(x[i], x[i + 1]);
+  *(double2*)(zp + 12) = make_double2(x[12], 0.0);
+  *(double2*)(zp + 14) = make_double2(0.0, 0.0);
+  *(double2*)(zp + 16) = make_double2(u[0], u[1]);
+  *(double2*)(zp + 18) = make_double2(u[2], u[3]);
+}
 
 __device__ __forceinline__ void load_z(const float* zp, float* z) {
   const float4 a = *(const float4*)(zp);
@@ -109,11 +172,11 @@ __device__ __forceinline__ void store_z(float* zp, const float* x, const float* 
   *(float4*)(zp + 16) = make_float4(u[0], u[1], u[2], u[3]);
 }
 
-__device__ __forceinline__ Grp make_grp(const KArgs& A, int slot, int l) {
+__device__ __forceinline__ Grp make_grp(const KArgs& A, int slot, int l, int nb = -1) {
   Grp G;
   G.l = l;
   G.col = (l == 0) ? 16 : l;
-  G.valid = slot < A.B;
+  G.valid = slot < (nb < 0 ? A.B : nb);
   G.b = G.valid ? (A.use_order ? A.ws.order[slot] : slot) : 0;
   int T = A.Tm;
   if (G.valid && A.T) T = A.T[G.b];
@@ -129,17 +192,23 @@ __device__ __forceinline__ Grp make_grp(const KArgs& A, int slot, int l) {
 
 // initial nominal (Alg. 2, Rollout): U^0 = clamp(warm start, or m g / 4 without
 // one), X^0 by RK4
+template <class R = float>
 __device__ void grp_init(const KArgs& A, const Grp& G) {
-  float x[NX], xn[NX], u[NU];
+  R x[NX], xn[NX], u[NU];
 #pragma unroll
-  for (int i = 0; i < NX; ++i) x[i] = A.x0[(size_t)G.b * NX + i];
+  for (int i = 0; i < NX; ++i) x[i] = (R)A.x0[(size_t)G.b * NX + i];
   for (int t = 0; t < G.T; ++t) {
     const float* ui = A.uinit ? A.uinit + ((size_t)G.b * A.Tm + t) * NU : nullptr;
 #pragma unroll
-    for (int a = 0; a < NU; ++a) u[a] = clampf(ui ? ui[a] : A.P.hover, G.lo[a], G.hi[a]);
-    if (G.l == 0) store_z(traj_at(A, G.b, 0, t), x, u);
+    for (int a = 0; a < NU; ++a) {
+      if constexpr (sizeof(R) == sizeof(float))
+        u[a] = clampf(ui ? ui[a] : A.P.hover, G.lo[a], G.hi[a]);
+      else
+        u[a] = clampd(ui ? (double)ui[a] : A.P64.hover, (double)G.lo[a], (double)G.hi[a]);
+    }
+    if (G.l == 0) store_z(traj_at<R>(A, G.b, 0, t), x, u);
     if (t + 1 < G.T) {
-      rk4(A.P, x, u, xn);
+      rk4(dyn_of<R>(A), x, u, xn);
 #pragma unroll
       for (int i = 0; i < NX; ++i) x[i] = xn[i];
     }
@@ -282,7 +351,7 @@ template <int N, class F>
 __device__ __forceinline__ void sfor(F&& f) {
   sfor_impl(std::make_integer_sequence<int, N>{}, f);
 }
-template <bool DENSE, int MODE, bool LIN_INLINE>
+template <bool DENSE, int MODE, bool LIN_INLINE, class R = float>
 __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* L, uint32_t& st, int t_hi,
                           int t_lo = 0, const double* vinit = nullptr, int tbase = 0) {
   const int l = G.l, col = G.col, b = G.b, T = G.T;
@@ -291,8 +360,8 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
 #pragma unroll
   for (int j = 0; j < NX; ++j) Vr[j] = (vinit && l < NX) ? vinit[l * 14 + j] : 0.0;
   if (vinit && l < NX) vl = vinit[CK_VV + l];
-  float zn[NZ];
-  if (t_hi > t_lo) load_z(traj_at(A, b, n, t_hi - 1), zn);
+  R zn[NZ];
+  if (t_hi > t_lo) load_z(traj_at<R>(A, b, n, t_hi - 1), zn);
   __builtin_amdgcn_s_waitcnt(0);  // no load pending on loop entry (see grp_ls)
   for (int t = t_hi - 1; t >= t_lo; --t) {
     if (MODE == 2 && t + 1 < T && (t + 1) % A.ckpt == 0) {
@@ -304,12 +373,12 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
         ck[CK_VV + l] = vl;
       }
     }
-    const float* zp = traj_at(A, b, n, t);
+    const R* zp = traj_at<R>(A, b, n, t);
     // this stage's own scalars are loaded before the next stage's nominal: the
     // vector-memory counter is in order, so they can then be waited for
     // without also waiting for the prefetch
     const size_t srow0 = (size_t)b * A.Tm + t;
-    const float s_zc = zp[col < NX ? col : col + 3];
+    const R s_zc = zp[col < NX ? col : col + 3];
     const float s_qc = DENSE ? 0.f : A.Q[srow0 * NZ + col];
     const float s_q0 = DENSE ? 0.f : A.Q[srow0 * NZ];
     const float s_pc = A.p[srow0 * NZ + col];
@@ -320,21 +389,21 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     // wait also cover the loads issued after it.  The previous iteration's k
     // (the box-QP's warm start) is read at every iteration and ignored at the
     // first; at the last stage the "next" nominal is this stage's again.
-    float4 s_kw = make_float4(0.f, 0.f, 0.f, 0.f);
+    decltype(ld4((const R*)nullptr)) s_kw = {R(0), R(0), R(0), R(0)};
     if (MODE == 0) {
-      const float4 w = *(const float4*)(gains_at(A, b, t) + 64);
+      const auto w = ld4(gains_at<R>(A, b, t) + 64);
       if (kit > 0) s_kw = w;
     }
-    float zb[NZ];
+    R zb[NZ];
 #pragma unroll
     for (int i = 0; i < NZ; ++i) zb[i] = zn[i];
-    load_z(traj_at(A, b, n, t > t_lo ? t - 1 : t), zn);
+    load_z(traj_at<R>(A, b, n, t > t_lo ? t - 1 : t), zn);
     const bool has_dyn = (t + 1 < T);
-    float Fc[NX];
+    R Fc[NX];
     if (has_dyn) {
       if (LIN_INLINE) {
-        const LaneDir D = make_dir(A.P, col);
-        rk4_column(A.P, zb, zb + NX, D, Fc);
+        const LaneDir<R> D = make_dir(dyn_of<R>(A), col);
+        rk4_column(dyn_of<R>(A), zb, zb + NX, D, Fc);
       } else {
         const float* fp = lin_at(A, b, t) + col * 16;
 #pragma unroll
@@ -342,15 +411,15 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < NX; ++k) Fc[k] = 0.f;
+      for (int k = 0; k < NX; ++k) Fc[k] = R(0);
     }
     if (MODE == 1) {
       float* tp = tail_at(A, b, t - tbase);
       float* fc = tp + col * 16;
-      *(float4*)(fc) = make_float4(Fc[0], Fc[1], Fc[2], Fc[3]);
-      *(float4*)(fc + 4) = make_float4(Fc[4], Fc[5], Fc[6], Fc[7]);
-      *(float4*)(fc + 8) = make_float4(Fc[8], Fc[9], Fc[10], Fc[11]);
-      fc[12] = Fc[12];
+      *(float4*)(fc) = make_float4((float)Fc[0], (float)Fc[1], (float)Fc[2], (float)Fc[3]);
+      *(float4*)(fc + 4) = make_float4((float)Fc[4], (float)Fc[5], (float)Fc[6], (float)Fc[7]);
+      *(float4*)(fc + 8) = make_float4((float)Fc[8], (float)Fc[9], (float)Fc[10], (float)Fc[11]);
+      fc[12] = (float)Fc[12];
       if (l == NX) {  // column 0 = e_0 (zero at the last stage)
         const float e = has_dyn ? 1.f : 0.f;
         *(float4*)(tp) = make_float4(e, 0.f, 0.f, 0.f);
@@ -459,7 +528,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
 
     double kv[4] = {0.0, 0.0, 0.0, 0.0}, fr[4];
     Fact4 C;
-    float* gp = gains_at(A, b, t);
+    R* gp = gains_at<R>(A, b, t);
     if (MODE == 0) {
       double kw[4] = {0.0, 0.0, 0.0, 0.0};
       kw[0] = s_kw.x; kw[1] = s_kw.y; kw[2] = s_kw.z; kw[3] = s_kw.w;
@@ -487,7 +556,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     solve4(C, Kd);
 #pragma unroll
     for (int a = 0; a < 4; ++a) Kd[a] = -Kd[a];
-    const float Kc[4] = {(float)Kd[0], (float)Kd[1], (float)Kd[2], (float)Kd[3]};
+    const R Kc[4] = {(R)Kd[0], (R)Kd[1], (R)Kd[2], (R)Kd[3]};
     // V row l = Q_xx[l, :] + Q_ux[:, l]^T K ;  v_l = Q_x[l] + Q_ux[:, l]^T k
     // (gain column j broadcast from lane j).  V is kept exactly symmetric:
     // lane l forms the entries j >= l of its row and writes each to (l, j) and
@@ -528,7 +597,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
       // writes the same k
 #pragma unroll
       for (int a = 0; a < 4; ++a) gp[a * 16 + l] = Kc[a];
-      *(float4*)(gp + 64) = make_float4((float)kv[0], (float)kv[1], (float)kv[2], (float)kv[3]);
+      st4(gp + 64, (R)kv[0], (R)kv[1], (R)kv[2], (R)kv[3]);
       if ((A.dlog || A.ws.pat) && l == 0) {
         unsigned code = 0;
 #pragma unroll
@@ -541,7 +610,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
       }
     } else if (MODE == 1) {
       float* tp = tail_at(A, b, t - tbase);
-      if (l < NX) *(float4*)(tp + FS + l * 4) = make_float4(Kc[0], Kc[1], Kc[2], Kc[3]);
+      if (l < NX) *(float4*)(tp + FS + l * 4) = make_float4((float)Kc[0], (float)Kc[1], (float)Kc[2], (float)Kc[3]);
       // M = masked inverse of the free block (zero rows/columns on clamped controls), FP64
       if (l == NX + 1) {
         double M[16];
@@ -568,28 +637,37 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
 // the quad shares the four controls, rolls the state out and sums the cost.
 // The next stage's nominal, gain row and cost are loaded while the current
 // stage is computed.
-template <bool DENSE>
+template <bool DENSE, class R = float>
 struct LsStage {
-  float xb[NX];
-  float ub, kr;
-  float Kr[NX];
+  R xb[NX];
+  R ub, kr;
+  R Kr[NX];
   float q[DENSE ? 1 : NZ];
   float p[NZ];
 };
 
-template <bool DENSE>
-__device__ __forceinline__ void ls_load(const KArgs& A, int b, int n, int t, int r, LsStage<DENSE>& S) {
-  const float* zp = traj_at(A, b, n, t);
-  const float4 a0 = *(const float4*)(zp), a1 = *(const float4*)(zp + 4), a2 = *(const float4*)(zp + 8);
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float clampR(float v, float lo, float hi) { return clampf(v, lo, hi); }
+__device__ __forceinline__ double clampR(double v, float lo, float hi) { return clampd(v, (double)lo, (double)hi); }
+__device__ __forceinline__ float absR(float v) { return fabsf(v); }
+__device__ __forceinline__ double absR(double v) { return fabs(v); }
+__device__ __forceinline__ float maxR(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double maxR(double a, double b) { return fmax(a, b); }
+
+template <bool DENSE, class R>
+__device__ __forceinline__ void ls_load(const KArgs& A, int b, int n, int t, int r, LsStage<DENSE, R>& S) {
+  const R* zp = traj_at<R>(A, b, n, t);
+  const auto a0 = ld4(zp), a1 = ld4(zp + 4), a2 = ld4(zp + 8);
   S.xb[0] = a0.x; S.xb[1] = a0.y; S.xb[2] = a0.z; S.xb[3] = a0.w;
   S.xb[4] = a1.x; S.xb[5] = a1.y; S.xb[6] = a1.z; S.xb[7] = a1.w;
   S.xb[8] = a2.x; S.xb[9] = a2.y; S.xb[10] = a2.z; S.xb[11] = a2.w;
   S.xb[12] = zp[12];
   S.ub = zp[16 + r];
-  const float* gp = gains_at(A, b, t);
+  const R* gp = gains_at<R>(A, b, t);
   S.kr = gp[64 + r];
-  const float* kp = gp + r * 16;
-  const float4 k0 = *(const float4*)(kp), k1 = *(const float4*)(kp + 4), k2 = *(const float4*)(kp + 8);
+  const R* kp = gp + r * 16;
+  const auto k0 = ld4(kp), k1 = ld4(kp + 4), k2 = ld4(kp + 8);
   S.Kr[0] = k0.x; S.Kr[1] = k0.y; S.Kr[2] = k0.z; S.Kr[3] = k0.w;
   S.Kr[4] = k1.x; S.Kr[5] = k1.y; S.Kr[6] = k1.z; S.Kr[7] = k1.w;
   S.Kr[8] = k2.x; S.Kr[9] = k2.y; S.Kr[10] = k2.z; S.Kr[11] = k2.w;
@@ -607,19 +685,19 @@ __device__ __forceinline__ void ls_load(const KArgs& A, int b, int n, int t, int
 
 // one stage of the line search: control, cost and stage record from cur and
 // the state x, prefetch of the next stage into nxt, the next state into xn
-template <bool DENSE>
-__device__ __forceinline__ void ls_stage(const KArgs& A, int b, int n, int t, int T, int r, int sc, float alpha,
-                                         float lo_r, float hi_r, const LsStage<DENSE>& cur, LsStage<DENSE>& nxt,
-                                         const float* x, float* xn, float& J, float& dm) {
+template <bool DENSE, class R>
+__device__ __forceinline__ void ls_stage(const KArgs& A, int b, int n, int t, int T, int r, int sc, R alpha,
+                                         float lo_r, float hi_r, const LsStage<DENSE, R>& cur,
+                                         LsStage<DENSE, R>& nxt, const R* x, R* xn, R& J, R& dm) {
   // the next stage's record (at the last stage this one's again: no branch
   // around the loads, which keeps the wait counts exact)
-  ls_load<DENSE>(A, b, n, t + 1 < T ? t + 1 : t, r, nxt);
-  float ur = cur.ub + alpha * cur.kr;
+  ls_load<DENSE, R>(A, b, n, t + 1 < T ? t + 1 : t, r, nxt);
+  R ur = cur.ub + alpha * cur.kr;
 #pragma unroll
-  for (int j = 0; j < NX; ++j) ur = fmaf(cur.Kr[j], x[j] - cur.xb[j], ur);
-  ur = clampf(ur, lo_r, hi_r);
-  dm = fmaxf(dm, fabsf(ur - cur.ub));
-  float z[NZ];
+  for (int j = 0; j < NX; ++j) ur = fmaR(cur.Kr[j], x[j] - cur.xb[j], ur);
+  ur = clampR(ur, lo_r, hi_r);
+  dm = maxR(dm, absR(ur - cur.ub));
+  R z[NZ];
 #pragma unroll
   for (int i = 0; i < NX; ++i) z[i] = x[i];
 #pragma unroll
@@ -627,43 +705,51 @@ __device__ __forceinline__ void ls_stage(const KArgs& A, int b, int n, int t, in
   const size_t srow = (size_t)b * A.Tm + t;
   if (!DENSE) {
 #pragma unroll
-    for (int i = 0; i < NZ; ++i) J = fmaf(fmaf(0.5f * cur.q[i], z[i], cur.p[i]), z[i], J);
+    for (int i = 0; i < NZ; ++i) J = fmaR(fmaR(R(0.5) * (R)cur.q[i], z[i], (R)cur.p[i]), z[i], J);
   } else {
     const float* crow = A.Q + srow * NPK;
     int m = 0;
 #pragma unroll
     for (int i = 0; i < NZ; ++i) {
-      float s = 0.5f * crow[m++] * z[i];
+      R s = R(0.5) * (R)crow[m++] * z[i];
 #pragma unroll
-      for (int j = i + 1; j < NZ; ++j) s = fmaf(crow[m++], z[j], s);
-      J = fmaf(s + cur.p[i], z[i], J);
+      for (int j = i + 1; j < NZ; ++j) s = fmaR((R)crow[m++], z[j], s);
+      J = fmaR(s + (R)cur.p[i], z[i], J);
     }
   }
   {
-    // lane r of the quad writes floats 4r..4r+3 of the stage record
-    float* zo = traj_at(A, b, sc, t);
-    const float4 w = r == 0 ? make_float4(x[0], x[1], x[2], x[3])
-                   : (r == 1 ? make_float4(x[4], x[5], x[6], x[7])
-                   : (r == 2 ? make_float4(x[8], x[9], x[10], x[11]) : make_float4(x[12], 0.f, 0.f, 0.f)));
-    *(float4*)(zo + 4 * r) = w;
+    // lane r of the quad writes entries 4r..4r+3 of the stage record
+    R* zo = traj_at<R>(A, b, sc, t);
+    if constexpr (sizeof(R) == sizeof(float)) {
+      const float4 w = r == 0 ? make_float4(x[0], x[1], x[2], x[3])
+                     : (r == 1 ? make_float4(x[4], x[5], x[6], x[7])
+                     : (r == 2 ? make_float4(x[8], x[9], x[10], x[11]) : make_float4(x[12], 0.f, 0.f, 0.f)));
+      *(float4*)(zo + 4 * r) = w;
+    } else {
+      const R w0 = r == 0 ? x[0] : (r == 1 ? x[4] : (r == 2 ? x[8] : x[12]));
+      const R w1 = r == 0 ? x[1] : (r == 1 ? x[5] : (r == 2 ? x[9] : R(0)));
+      const R w2 = r == 0 ? x[2] : (r == 1 ? x[6] : (r == 2 ? x[10] : R(0)));
+      const R w3 = r == 0 ? x[3] : (r == 1 ? x[7] : (r == 2 ? x[11] : R(0)));
+      st4(zo + 4 * r, w0, w1, w2, w3);
+    }
     // all four lanes write the same controls: no branch around the store
-    *(float4*)(zo + 16) = make_float4(z[13], z[14], z[15], z[16]);
+    st4(zo + 16, z[13], z[14], z[15], z[16]);
   }
-  if (t + 1 < T) rk4(A.P, x, z + NX, xn);
+  if (t + 1 < T) rk4(dyn_of<R>(A), x, z + NX, xn);
 }
 
-template <bool DENSE>
-__device__ void grp_ls(const KArgs& A, const Grp& G, int n, float& Jout, float& dmax) {
+template <bool DENSE, class R = float>
+__device__ void grp_ls(const KArgs& A, const Grp& G, int n, R& Jout, R& dmax) {
   const int a = G.l >> 2, r = G.l & 3, b = G.b, T = G.T;
-  const float alpha = a == 0 ? 1.f : (a == 1 ? 0.5f : (a == 2 ? 0.25f : 0.1f));
+  const R alpha = a == 0 ? R(1) : (a == 1 ? R(0.5) : (a == 2 ? R(0.25) : R(0.1)));
   const int sc = (n + 1 + a) % NSLOT;
   const float lo_r = A.lo[(size_t)b * NU + r], hi_r = A.hi[(size_t)b * NU + r];
-  float x[NX], xn[NX];
+  R x[NX], xn[NX];
 #pragma unroll
-  for (int i = 0; i < NX; ++i) x[i] = A.x0[(size_t)b * NX + i];
-  float J = 0.f, dm = 0.f;
-  LsStage<DENSE> sa, sb;
-  if (T > 0) ls_load<DENSE>(A, b, n, 0, r, sa);
+  for (int i = 0; i < NX; ++i) x[i] = (R)A.x0[(size_t)b * NX + i];
+  R J = R(0), dm = R(0);
+  LsStage<DENSE, R> sa, sb;
+  if (T > 0) ls_load<DENSE, R>(A, b, n, 0, r, sa);
   // Let the first stage's loads land before the loop: with loads still
   // pending on entry, the wait counters inside the loop have to assume that
   // any register could be one of them, and (the vector-memory counter being
@@ -672,9 +758,9 @@ __device__ void grp_ls(const KArgs& A, const Grp& G, int n, float& Jout, float& 
   // two stages per trip with the stage records and the state swapping roles,
   // so that nothing is copied from one stage to the next
   for (int t = 0; t < T; t += 2) {
-    ls_stage<DENSE>(A, b, n, t, T, r, sc, alpha, lo_r, hi_r, sa, sb, x, xn, J, dm);
+    ls_stage<DENSE, R>(A, b, n, t, T, r, sc, alpha, lo_r, hi_r, sa, sb, x, xn, J, dm);
     if (t + 1 >= T) break;
-    ls_stage<DENSE>(A, b, n, t + 1, T, r, sc, alpha, lo_r, hi_r, sb, sa, xn, x, J, dm);
+    ls_stage<DENSE, R>(A, b, n, t + 1, T, r, sc, alpha, lo_r, hi_r, sb, sa, xn, x, J, dm);
   }
   Jout = J;  // all four lanes of a quad hold the same cost
   dmax = quad_max(dm);
@@ -683,15 +769,21 @@ __device__ void grp_ls(const KArgs& A, const Grp& G, int n, float& Jout, float& 
 __device__ __forceinline__ float finite_or_inf(float v) {
   return (v == v && fabsf(v) <= 3.402823466e38f) ? v : INFINITY;
 }
+__device__ __forceinline__ double finite_or_inf(double v) {
+  return (v == v && fabs(v) <= 1.7976931348623157e308) ? v : (double)INFINITY;
+}
+__device__ __forceinline__ float rbR(float v, int L) { return rb(v, L); }
+__device__ __forceinline__ double rbR(double v, int L) { return rb64(v, L); }
 
 // pick the first minimiser of the four candidate costs; returns -1 if none is finite
-__device__ __forceinline__ int ls_select(float J, float dm, float& dsel) {
-  const float c0 = finite_or_inf(rb(J, 0)), c1 = finite_or_inf(rb(J, 4)), c2 = finite_or_inf(rb(J, 8)),
-              c3 = finite_or_inf(rb(J, 12));
-  const float d0 = rb(dm, 0), d1 = rb(dm, 4), d2 = rb(dm, 8), d3 = rb(dm, 12);
+template <class R>
+__device__ __forceinline__ int ls_select(R J, R dm, R& dsel) {
+  const R c0 = finite_or_inf(rbR(J, 0)), c1 = finite_or_inf(rbR(J, 4)), c2 = finite_or_inf(rbR(J, 8)),
+          c3 = finite_or_inf(rbR(J, 12));
+  const R d0 = rbR(dm, 0), d1 = rbR(dm, 4), d2 = rbR(dm, 8), d3 = rbR(dm, 12);
   int best = -1;
-  float bj = INFINITY;
-  dsel = 0.f;
+  R bj = (R)INFINITY;
+  dsel = R(0);
   if (c0 < bj) { best = 0; bj = c0; dsel = d0; }
   if (c1 < bj) { best = 1; bj = c1; dsel = d1; }
   if (c2 < bj) { best = 2; bj = c2; dsel = d2; }
@@ -702,6 +794,7 @@ __device__ __forceinline__ int ls_select(float J, float dm, float& dsel) {
 // writes u_out / x_out (zeros past T_b) from the nominal slot
 // (the 16 lanes take the stage entries in turn, eight loads in flight before
 // their stores: the outputs may alias nothing, but the compiler cannot know)
+template <class R = float>
 __device__ void grp_outputs(const KArgs& A, const Grp& G, int n) {
   const int b = G.b, total = A.Tm * NZ;
   for (int i0 = G.l; i0 < total; i0 += 16 * 8) {
@@ -709,7 +802,7 @@ __device__ void grp_outputs(const KArgs& A, const Grp& G, int n) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int i = i0 + 16 * j, t = i / NZ, e = i % NZ;
-      v[j] = (i < total && t < G.T) ? traj_at(A, b, n, t)[e < NX ? e : e + 3] : 0.f;
+      v[j] = (i < total && t < G.T) ? (float)traj_at<R>(A, b, n, t)[e < NX ? e : e + 3] : 0.f;
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -742,30 +835,35 @@ __device__ __forceinline__ void grp_write_state(const KArgs& A, const Grp& G, in
 // OCC: waves per SIMD the register allocation is capped for (1: no cap beyond
 // the 512-register file; 2: at most 256 registers, two waves share a SIMD and
 // hide each other's latency when there are more waves than SIMDs).
-template <bool DENSE, int OCC>
+// R: precision of the dynamics, the linearisation, the line search and the
+// stored trajectories and gains (float; double in the FP64 form).
+template <bool DENSE, int OCC, class R = float>
 __global__ __launch_bounds__(64, OCC) void k_fwd_persistent(KArgs A) {
   __shared__ double lds[4 * L_REG];
   const int lane = threadIdx.x, grp = lane >> 4, l = lane & 15;
   double* L = lds + grp * L_REG;
+  // an FP64 redo takes the flagged instances listed in ws.order
+  const int nb = A.redo_count ? __builtin_amdgcn_readfirstlane(*A.redo_count) : A.B;
+  const int nq = (nb + 3) >> 2;
   for (;;) {
     int q = 0;
     if (lane == 0) q = atomicAdd(A.ws.queue, 1);
     q = __builtin_amdgcn_readfirstlane(q);
-    if (q >= A.nquads) break;
-    const Grp G = make_grp(A, q * 4 + grp, l);
+    if (q >= nq) break;
+    const Grp G = make_grp(A, q * 4 + grp, l, nb);
     if (!G.valid) continue;
     uint32_t st = 0;
     int n = 0, iters = 0;
     if (G.T > 0) {
-      grp_init(A, G);
+      grp_init<R>(A, G);
       mem_fence_wg();
       bool done = false;
       for (int k = 0; k < A.K; ++k) {
         if (done) continue;
-        grp_sweep<DENSE, 0, true>(A, G, n, k, L, st, G.T);
+        grp_sweep<DENSE, 0, true, R>(A, G, n, k, L, st, G.T);
         mem_fence_wg();
-        float J, dm, dsel;
-        grp_ls<DENSE>(A, G, n, J, dm);
+        R J, dm, dsel;
+        grp_ls<DENSE, R>(A, G, n, J, dm);
         mem_fence_wg();
         const int best = ls_select(J, dm, dsel);
         if (A.dlog && l == 0) A.dlog[((size_t)G.b * A.K + k) * (1 + A.Tm)] = best < 0 ? 255 : (uint8_t)best;
@@ -774,7 +872,7 @@ __global__ __launch_bounds__(64, OCC) void k_fwd_persistent(KArgs A) {
           st |= ST_NONFINITE;
         } else {
           n = (n + 1 + best) % NSLOT;
-          if (A.tol > 0.f && dsel < A.tol) {
+          if (A.tol > 0.f && dsel < (R)A.tol) {
             st |= ST_CONVERGED;
             done = true;
           }
@@ -782,14 +880,40 @@ __global__ __launch_bounds__(64, OCC) void k_fwd_persistent(KArgs A) {
       }
       if (A.tol > 0.f && !(st & ST_CONVERGED)) st |= ST_MAXITER;
       if (A.need_grad) {
-        if (A.ckpt > 0) grp_sweep<DENSE, 2, true>(A, G, n, 0, L, st, G.T);
-        else grp_sweep<DENSE, 1, true>(A, G, n, 0, L, st, G.T);
+        if (A.ckpt > 0) grp_sweep<DENSE, 2, true, R>(A, G, n, 0, L, st, G.T);
+        else grp_sweep<DENSE, 1, true, R>(A, G, n, 0, L, st, G.T);
       }
     }
-    grp_outputs(A, G, n);
+    grp_outputs<R>(A, G, n);
+    if constexpr (sizeof(R) == sizeof(double)) {
+      if (A.traj_f) {
+        // FP64 redo: the final nominal, rounded, into the float region the
+        // backward reads
+        const R* src = traj_at<R>(A, G.b, n, 0);
+        float* dst = A.traj_f + ((size_t)G.b * NSLOT + n) * A.Tm * ZS;
+        for (int i = l; i < G.T * ZS; i += 16) dst[i] = (float)src[i];
+        st |= ST_REDONE;
+      }
+    }
     grp_write_state(A, G, n, iters, st, 1);
     if (l == 0) A.status[G.b] = st | ((uint32_t)iters << DMPC_ST_ITERS_SHIFT);
   }
+}
+
+// FP64 redo: resets the redo list's count and queue counter
+__global__ void k_reset_redo(int* count, int* queue) {
+  if (threadIdx.x == 0) {
+    *count = 0;
+    *queue = 0;
+  }
+}
+
+// FP64 redo: the instances whose control block had a pivot below the
+// threshold, in any order (each instance's result does not depend on the
+// wave that solves it)
+__global__ __launch_bounds__(256) void k_redo_list(const uint32_t* status, int B, int* list, int* count) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b < B && (status[b] & ST_FP64)) list[atomicAdd(count, 1)] = b;
 }
 
 __global__ void k_reset_queue(int* queue) {
@@ -1509,7 +1633,7 @@ __constant__ PackTable c_pk = make_pack_table();
 // the backward vector sweep and first segment first for the forward sweep.
 // The checkpoint is the exact FP64 state of the forward's sweep, so the
 // recomputed factors are the ones the forward would have stored.
-template <bool DENSE, bool CKPT, bool THETA>
+template <bool DENSE, bool CKPT, bool THETA, class R = float>
 __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
   __shared__ float zz[4][2][20];
   __shared__ double lds[CKPT ? 4 * L_REG : 2];
@@ -1539,7 +1663,7 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
   auto recompute = [&](int a, int e) {
     uint32_t st = 0;
     const double* vinit = (e < T) ? A.ws.ck + ((size_t)b * A.nck + (e / seg - 1)) * CK_W : nullptr;
-    grp_sweep<DENSE, 1, true>(A, G, n, 0, L, st, e, a, vinit, a);
+    grp_sweep<DENSE, 1, true, R>(A, G, n, 0, L, st, e, a, vinit, a);
     mem_fence_wg();
   };
   // backward vector sweep: q~ = d + F^T v, k~ = -M q~_u, v = q~_x + K^T q~_u.
@@ -1639,7 +1763,14 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
     S.kk = *(const float4*)(A.ws.ktil + srow * 4);
 #pragma unroll
     for (int j = 0; j < NX; ++j) S.K[j] = *(const float4*)(tp + FS + j * 4);
-    load_z(traj_at(A, b, n, t), S.zs);
+    if constexpr (sizeof(R) == sizeof(float)) {
+      load_z(traj_at<float>(A, b, n, t), S.zs);
+    } else {
+      R zd[NZ];
+      load_z(traj_at<R>(A, b, n, t), zd);
+#pragma unroll
+      for (int i = 0; i < NZ; ++i) S.zs[i] = (float)zd[i];
+    }
     // row l of F = [A | B]: column c stored at c * 16
 #pragma unroll
     for (int c = 0; c < NZ; ++c) S.fr[c] = tp[c * 16 + (l < NX ? l : 0)];
@@ -1827,9 +1958,9 @@ __global__ __launch_bounds__(64) void k_mpc_step(Dyn P, int B, int Tm, const int
 // ---------------------------------------------------------------------------
 
 struct Layout {
-  size_t state, queue, order, traj, gains, lin, tail, ktil, ck, elem, pat, total;
+  size_t state, queue, order, traj, gains, lin, tail, ktil, ck, elem, pat, traj64, gains64, total;
   int tstride, nck;
-  bool has_lin, has_tpar;
+  bool has_lin, has_tpar, has_redo;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -1841,7 +1972,10 @@ int check_cfg(const dmpc_config* c) {
   if (c->cost_kind != DMPC_COST_DIAG && c->cost_kind != DMPC_COST_DENSE) return DMPC_EUNSUPPORTED;
   if (c->ckpt_every < 0) return DMPC_EINVAL;
   if (!(c->tol_du == c->tol_du) || !(c->fp64_pivot == c->fp64_pivot)) return DMPC_EINVAL;
-  if (c->flags & ~(DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT | DMPC_TUNED | DMPC_TPAR)) return DMPC_EINVAL;
+  if (c->flags & ~(DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT | DMPC_TUNED | DMPC_TPAR | DMPC_F64 | DMPC_F64_REDO))
+    return DMPC_EINVAL;
+  if ((c->flags & (DMPC_F64 | DMPC_F64_REDO)) && (c->flags & (DMPC_PLAIN | DMPC_TPAR))) return DMPC_EUNSUPPORTED;
+  if ((c->flags & DMPC_F64) && (c->flags & DMPC_F64_REDO)) return DMPC_EINVAL;
   return DMPC_OK;
 }
 
@@ -1857,8 +1991,10 @@ Layout make_layout(const dmpc_config* c) {
   L.state = take(B * SW * sizeof(int));
   L.queue = take(256);
   L.order = take(B * sizeof(int));
-  L.traj = take(B * NSLOT * Tm * ZS * sizeof(float));
-  L.gains = take(B * Tm * GS * sizeof(float));
+  // trajectories and gains in the dynamics precision
+  const size_t rs = (c->flags & DMPC_F64) ? sizeof(double) : sizeof(float);
+  L.traj = take(B * NSLOT * Tm * ZS * rs);
+  L.gains = take(B * Tm * GS * rs);
   // the per-launch form's linearisation buffer: present when that form may run
   // (requested, or possibly chosen by a tuned launch)
   L.has_lin = (c->flags & (DMPC_PLAIN | DMPC_TUNED | DMPC_TPAR)) != 0;
@@ -1876,8 +2012,33 @@ Layout make_layout(const dmpc_config* c) {
   L.tail = take(g ? B * (size_t)L.tstride * TS * sizeof(float) : 0);
   L.ktil = take(g ? B * Tm * 4 * sizeof(float) : 0);
   L.ck = take(g ? B * (size_t)L.nck * CK_W * sizeof(double) : 0);
+  // the FP64 redo's own trajectories and gains
+  L.has_redo = (c->flags & DMPC_F64_REDO) != 0;
+  L.traj64 = take(L.has_redo ? B * NSLOT * Tm * ZS * sizeof(double) : 0);
+  L.gains64 = take(L.has_redo ? B * Tm * GS * sizeof(double) : 0);
   L.total = off;
   return L;
+}
+
+// the same constants formed in double from the float inputs
+Dyn64 make_dyn64(const dmpc_quad_params& q) {
+  Dyn64 P;
+  const double mass = q.mass, Jxx = q.Jxx, Jyy = q.Jyy, Jzz = q.Jzz, dt = q.dt;
+  P.h = dt;
+  P.h2 = 0.5 * dt;
+  P.h6 = dt / 6.0;
+  P.g = q.g;
+  P.inv_m = 1.0 / mass;
+  P.arm_a = (double)q.arm / std::sqrt(2.0);
+  P.kappa = q.kappa;
+  P.iJx = 1.0 / Jxx;
+  P.iJy = 1.0 / Jyy;
+  P.iJz = 1.0 / Jzz;
+  P.cx = (Jzz - Jyy) / Jxx;
+  P.cy = (Jxx - Jzz) / Jyy;
+  P.cz = (Jyy - Jxx) / Jzz;
+  P.hover = mass * (double)q.g / 4.0;
+  return P;
 }
 
 Dyn make_dyn(const dmpc_quad_params& q) {
@@ -1906,6 +2067,7 @@ thread_local std::string g_err;
 struct dmpc_handle_s {
   int device = 0;
   int cu = 0;
+  std::string arch;  // the device's architecture name (gcnArchName), keys saved launch choices
   int occ[2][2] = {{1, 1}, {1, 1}};  // resident workgroups per CU: [dense][waves-per-SIMD variant]
   int last_launches = 0;
   dmpc_launch_choice last_choice{};
@@ -1974,6 +2136,8 @@ KArgs base_args(const dmpc_config* c, void* workspace) {
   A.ws.ck = (double*)(w + L.ck);
   A.ws.elem = L.has_tpar ? (double*)(w + L.elem) : nullptr;
   A.ws.pat = L.has_tpar ? (uint8_t*)(w + L.pat) : nullptr;
+  A.ws.traj64 = L.has_redo ? (float*)(w + L.traj64) : nullptr;
+  A.ws.gains64 = L.has_redo ? (float*)(w + L.gains64) : nullptr;
   A.ckpt = c->ckpt_every;
   A.nck = L.nck;
   A.tstride = L.tstride;
@@ -1982,8 +2146,10 @@ KArgs base_args(const dmpc_config* c, void* workspace) {
 }
 
 // problem shape a tuned launch choice applies to
+// (the flags field holds DMPC_NEED_GRAD, DMPC_F64 and DMPC_F64_REDO)
 std::array<int, 6> shape_key(const dmpc_config* c, bool has_T) {
-  return {c->B, c->T_max, c->cost_kind, (int)(c->flags & DMPC_NEED_GRAD), c->ckpt_every > 0 ? 1 : 0, has_T ? 1 : 0};
+  return {c->B, c->T_max, c->cost_kind, (int)(c->flags & (DMPC_NEED_GRAD | DMPC_F64 | DMPC_F64_REDO)),
+          c->ckpt_every > 0 ? 1 : 0, has_T ? 1 : 0};
 }
 
 dmpc_launch_choice default_choice(const dmpc_config* c) {
@@ -2015,6 +2181,7 @@ int forward_args(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, co
     return fail(h, DMPC_EWORKSPACE, "workspace missing, misaligned or smaller than dmpc_workspace_bytes()");
   A = base_args(cfg, workspace);
   A.P = make_dyn(dyn);
+  A.P64 = make_dyn64(dyn);
   A.x0 = x0;
   A.Q = Q;
   A.p = p;
@@ -2029,10 +2196,31 @@ int forward_args(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, co
   return DMPC_OK;
 }
 
-template <bool DENSE>
+template <class R>
+void launch_bwd(bool dense, bool ckpt, bool theta, int g, hipStream_t s, const KArgs& A) {
+  if (ckpt) {
+    if (theta) {
+      if (dense) k_bwd<true, true, true, R><<<g, 64, 0, s>>>(A);
+      else k_bwd<false, true, true, R><<<g, 64, 0, s>>>(A);
+    } else {
+      if (dense) k_bwd<true, true, false, R><<<g, 64, 0, s>>>(A);
+      else k_bwd<false, true, false, R><<<g, 64, 0, s>>>(A);
+    }
+  } else {
+    if (theta) {
+      if (dense) k_bwd<true, false, true, R><<<g, 64, 0, s>>>(A);
+      else k_bwd<false, false, true, R><<<g, 64, 0, s>>>(A);
+    } else {
+      if (dense) k_bwd<true, false, false, R><<<g, 64, 0, s>>>(A);
+      else k_bwd<false, false, false, R><<<g, 64, 0, s>>>(A);
+    }
+  }
+}
+
+template <bool DENSE, class R>
 void launch_persistent(int occ, int grid, hipStream_t s, const KArgs& A) {
-  if (occ == 2) k_fwd_persistent<DENSE, 2><<<grid, 64, 0, s>>>(A);
-  else k_fwd_persistent<DENSE, 1><<<grid, 64, 0, s>>>(A);
+  if (occ == 2) k_fwd_persistent<DENSE, 2, R><<<grid, 64, 0, s>>>(A);
+  else k_fwd_persistent<DENSE, 1, R><<<grid, 64, 0, s>>>(A);
 }
 
 int launch_forward(dmpc_handle h, const dmpc_config* cfg, KArgs A, const int32_t* T, const dmpc_launch_choice& c,
@@ -2040,6 +2228,9 @@ int launch_forward(dmpc_handle h, const dmpc_config* cfg, KArgs A, const int32_t
   const bool dense = cfg->cost_kind == DMPC_COST_DENSE;
   const int nq = A.nquads;
   int launches = 0;
+  const bool f64 = (cfg->flags & DMPC_F64) != 0, redo = (cfg->flags & DMPC_F64_REDO) != 0;
+  if (c.plain && (f64 || redo))
+    return fail(h, DMPC_EUNSUPPORTED, "the FP64 form (DMPC_F64, DMPC_F64_REDO) runs as the persistent launch only");
   if (c.plain && !A.has_lin)
     return fail(h, DMPC_EWORKSPACE, "the per-launch form needs a workspace sized with DMPC_PLAIN or DMPC_TUNED");
   if (c.plain == 2 && !A.ws.elem)
@@ -2104,9 +2295,33 @@ int launch_forward(dmpc_handle h, const dmpc_config* cfg, KArgs A, const int32_t
     const int occ = c.waves_per_simd == 2 ? 2 : 1;
     const int cap = std::max(1, h->cu * h->occ[dense ? 1 : 0][occ - 1]);
     const int grid = c.grid_mode == 1 ? nq : std::min(nq, cap);
-    if (dense) launch_persistent<true>(occ, grid, s, A);
-    else launch_persistent<false>(occ, grid, s, A);
+    if (f64) {
+      if (dense) launch_persistent<true, double>(occ, grid, s, A);
+      else launch_persistent<false, double>(occ, grid, s, A);
+    } else {
+      if (dense) launch_persistent<true, float>(occ, grid, s, A);
+      else launch_persistent<false, float>(occ, grid, s, A);
+    }
     launches += 2;
+    if (redo) {
+      // the instances whose control block had a pivot below fp64_pivot are
+      // solved again, from the start, in the FP64 form, in their own
+      // trajectory and gain regions; the instance list reuses ws.order (the
+      // FP32 launch no longer reads it) and the redo's counters sit in the
+      // queue block, apart from the FP32 launch's counter
+      KArgs Rd = A;
+      Rd.ws.traj = A.ws.traj64;
+      Rd.ws.gains = A.ws.gains64;
+      Rd.ws.queue = A.ws.queue + 32;
+      Rd.redo_count = A.ws.queue + 16;
+      Rd.traj_f = A.ws.traj;
+      Rd.use_order = 1;
+      k_reset_redo<<<1, 64, 0, s>>>(A.ws.queue + 16, A.ws.queue + 32);
+      k_redo_list<<<(cfg->B + 255) / 256, 256, 0, s>>>(A.status, cfg->B, A.ws.order, A.ws.queue + 16);
+      if (dense) launch_persistent<true, double>(occ, grid, s, Rd);
+      else launch_persistent<false, double>(occ, grid, s, Rd);
+      launches += 3;
+    }
   }
   h->last_launches = launches;
   h->last_choice = c;
@@ -2143,6 +2358,7 @@ int dmpc_create(dmpc_handle* out, int device) {
     return rc;
   }
   h->cu = prop.multiProcessorCount;
+  h->arch = prop.gcnArchName;
   DeviceScope scope(device);
   rc = hip_check(h, scope.status(), "hipSetDevice");
   if (rc) {
@@ -2207,8 +2423,9 @@ int dmpc_autotune(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, c
     // candidates: per-launch form (and its time-parallel variant when the
     // workspace has room for it); persistent form x occupancy target x grid x order
     std::vector<dmpc_launch_choice> cand;
-    if (A.has_lin) cand.push_back(dmpc_launch_choice{1, 0, 1, 0, 0.f});
-    if (A.ws.elem) cand.push_back(dmpc_launch_choice{2, 0, 1, 0, 0.f});
+    const bool f64 = (cfg->flags & (DMPC_F64 | DMPC_F64_REDO)) != 0;
+    if (A.has_lin && !f64) cand.push_back(dmpc_launch_choice{1, 0, 1, 0, 0.f});
+    if (A.ws.elem && !f64) cand.push_back(dmpc_launch_choice{2, 0, 1, 0, 0.f});
     for (int occ = 1; occ <= 2; ++occ)
       for (int grid = 0; grid <= 1; ++grid)
         for (int lpt = 0; lpt <= (T ? 1 : 0); ++lpt) cand.push_back(dmpc_launch_choice{0, lpt, occ, grid, 0.f});
@@ -2273,6 +2490,52 @@ int dmpc_get_tuned(dmpc_handle h, const dmpc_config* cfg, int has_T, dmpc_launch
   return DMPC_OK;
 }
 
+// One line per tuned shape:
+//   dmpc-tuned-v1 <arch> <cu> <B> <T_max> <cost_kind> <need_grad> <ckpt> <has_T> <plain> <lpt> <waves> <grid> <ms>
+int dmpc_tuned_save(dmpc_handle h, const char* path) {
+  if (!h || !path) return fail(h, DMPC_EINVAL, "NULL argument");
+  std::ostringstream o;
+  for (const auto& kv : h->tuned) {
+    const auto& k = kv.first;
+    const auto& c = kv.second;
+    o << "dmpc-tuned-v1 " << h->arch << ' ' << h->cu;
+    for (int v : k) o << ' ' << v;
+    o << ' ' << c.plain << ' ' << c.lpt << ' ' << c.waves_per_simd << ' ' << c.grid_mode << ' ' << c.ms << '\n';
+  }
+  std::ofstream f(path, std::ios::trunc);
+  if (!f) return fail(h, DMPC_EINVAL, std::string("cannot write ") + path);
+  f << o.str();
+  f.close();
+  if (!f) return fail(h, DMPC_EINVAL, std::string("cannot write ") + path);
+  return (int)h->tuned.size();
+}
+
+int dmpc_tuned_load(dmpc_handle h, const char* path) {
+  if (!h || !path) return fail(h, DMPC_EINVAL, "NULL argument");
+  std::ifstream f(path);
+  if (!f) return fail(h, DMPC_EINVAL, std::string("cannot read ") + path);
+  std::string line;
+  int n = 0;
+  while (std::getline(f, line)) {
+    std::istringstream in(line);
+    std::string tag, arch;
+    int cu = 0;
+    std::array<int, 6> k{};
+    dmpc_launch_choice c{};
+    if (!(in >> tag >> arch >> cu) || tag != "dmpc-tuned-v1") continue;
+    bool ok = true;
+    for (int& v : k) ok = ok && (bool)(in >> v);
+    ok = ok && (bool)(in >> c.plain >> c.lpt >> c.waves_per_simd >> c.grid_mode >> c.ms);
+    if (!ok || arch != h->arch || cu != h->cu) continue;
+    if (c.plain < 0 || c.plain > 2 || c.lpt < 0 || c.lpt > 1 || c.waves_per_simd < 1 || c.waves_per_simd > 2 ||
+        c.grid_mode < 0 || c.grid_mode > 1)
+      continue;
+    h->tuned[k] = c;
+    ++n;
+  }
+  return n;
+}
+
 int dmpc_last_launch_choice(dmpc_handle h, dmpc_launch_choice* choice) {
   if (!h || !choice) return fail(h, DMPC_EINVAL, "NULL argument");
   *choice = h->last_choice;
@@ -2316,29 +2579,17 @@ int dmpc_backward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, c
   const bool dense = cfg->cost_kind == DMPC_COST_DENSE;
   if (ckpt || theta) {
     A.P = make_dyn(dyn);
+    A.P64 = make_dyn64(dyn);
     A.Q = Q;
     A.p = p;
     A.lo = u_lo;
     A.hi = u_hi;
   }
   const int g = A.nquads;
-  if (ckpt) {
-    if (theta) {
-      if (dense) k_bwd<true, true, true><<<g, 64, 0, s>>>(A);
-      else k_bwd<false, true, true><<<g, 64, 0, s>>>(A);
-    } else {
-      if (dense) k_bwd<true, true, false><<<g, 64, 0, s>>>(A);
-      else k_bwd<false, true, false><<<g, 64, 0, s>>>(A);
-    }
-  } else {
-    if (theta) {
-      if (dense) k_bwd<true, false, true><<<g, 64, 0, s>>>(A);
-      else k_bwd<false, false, true><<<g, 64, 0, s>>>(A);
-    } else {
-      if (dense) k_bwd<true, false, false><<<g, 64, 0, s>>>(A);
-      else k_bwd<false, false, false><<<g, 64, 0, s>>>(A);
-    }
-  }
+  if (cfg->flags & DMPC_F64)
+    launch_bwd<double>(dense, ckpt, theta, g, s, A);
+  else
+    launch_bwd<float>(dense, ckpt, theta, g, s, A);
   h->last_launches = 1;
   return hip_check(h, hipGetLastError(), "kernel launch");
 }

@@ -29,11 +29,16 @@ constexpr int S_NOM = 0, S_ITERS = 1, S_STATUS = 2, S_DONE = 3, S_T = 4;
 constexpr int S_FB = 5;  // time-parallel Riccati: a stage's clamp pattern differed from the assumed one
 
 constexpr uint32_t ST_CONVERGED = 0x1u, ST_MAXITER = 0x2u, ST_NONFINITE = 0x4u, ST_FP64 = 0x8u,
-                   ST_QPMAXITER = 0x10u, ST_REGULARIZED = 0x20u;
+                   ST_QPMAXITER = 0x10u, ST_REGULARIZED = 0x20u, ST_REDONE = 0x40u;
 
-struct Dyn {
-  float h, h2, h6, g, inv_m, arm_a, kappa, iJx, iJy, iJz, cx, cy, cz, hover;
+// model constants in the precision R of the dynamics (float, or double in the
+// FP64 form)
+template <class R>
+struct DynT {
+  R h, h2, h6, g, inv_m, arm_a, kappa, iJx, iJy, iJz, cx, cy, cz, hover;
 };
+using Dyn = DynT<float>;
+using Dyn64 = DynT<double>;
 
 // ---------------------------------------------------------------------------
 // lane helpers (16-lane DPP rows)
@@ -99,6 +104,31 @@ __device__ __forceinline__ float quad_max(float v) {
   return v;
 }
 
+// 64-bit versions (two 32-bit DPP moves each)
+__device__ __forceinline__ double qb(double v, int Q) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __float_as_int(qb(__int_as_float((int)x), Q));
+  const int hi = __float_as_int(qb(__int_as_float((int)(x >> 32)), Q));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double dpp_b1(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double dpp_4e(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), 0x4E, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double quad_max(double v) {
+  v = fmax(v, dpp_b1(v));
+  v = fmax(v, dpp_4e(v));
+  return v;
+}
+
 // lane holding column j of F (j >= 1)
 __host__ __device__ constexpr int lane_of(int j) { return j == 16 ? 0 : j; }
 
@@ -106,7 +136,8 @@ __host__ __device__ constexpr int lane_of(int j) { return j == 16 ? 0 : j; }
 // quadrotor dynamics, its tangent, RK4
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void forces(const Dyn& P, const float* u, float& s, float& tx, float& ty, float& tz) {
+template <class R>
+__device__ __forceinline__ void forces(const DynT<R>& P, const R* u, R& s, R& tx, R& ty, R& tz) {
   s = (u[0] + u[1] + u[2] + u[3]) * P.inv_m;
   tx = P.arm_a * (u[0] + u[1] - u[2] - u[3]) * P.iJx;
   ty = P.arm_a * (-u[0] + u[1] + u[2] - u[3]) * P.iJy;
@@ -114,39 +145,41 @@ __device__ __forceinline__ void forces(const Dyn& P, const float* u, float& s, f
 }
 
 // xdot = F(x, u) with the input entering through (s, tx, ty, tz)
-__device__ __forceinline__ void rhs(const Dyn& P, const float* x, float s, float tx, float ty, float tz, float* o) {
-  const float qw = x[3], qx = x[4], qy = x[5], qz = x[6], wx = x[10], wy = x[11], wz = x[12];
+template <class R>
+__device__ __forceinline__ void rhs(const DynT<R>& P, const R* x, R s, R tx, R ty, R tz, R* o) {
+  const R qw = x[3], qx = x[4], qy = x[5], qz = x[6], wx = x[10], wy = x[11], wz = x[12];
   o[0] = x[7];
   o[1] = x[8];
   o[2] = x[9];
-  o[3] = 0.5f * (-qx * wx - qy * wy - qz * wz);
-  o[4] = 0.5f * (qw * wx + qy * wz - qz * wy);
-  o[5] = 0.5f * (qw * wy - qx * wz + qz * wx);
-  o[6] = 0.5f * (qw * wz + qx * wy - qy * wx);
-  o[7] = s * (2.f * (qx * qz + qw * qy));
-  o[8] = s * (2.f * (qy * qz - qw * qx));
-  o[9] = s * (1.f - 2.f * (qx * qx + qy * qy)) - P.g;
+  o[3] = R(0.5) * (-qx * wx - qy * wy - qz * wz);
+  o[4] = R(0.5) * (qw * wx + qy * wz - qz * wy);
+  o[5] = R(0.5) * (qw * wy - qx * wz + qz * wx);
+  o[6] = R(0.5) * (qw * wz + qx * wy - qy * wx);
+  o[7] = s * (R(2) * (qx * qz + qw * qy));
+  o[8] = s * (R(2) * (qy * qz - qw * qx));
+  o[9] = s * (R(1) - R(2) * (qx * qx + qy * qy)) - P.g;
   o[10] = tx - P.cx * wy * wz;
   o[11] = ty - P.cy * wz * wx;
   o[12] = tz - P.cz * wx * wy;
 }
 
 // directional derivative of F at (x, u) along (d, du), du entering as (ds, dtx, dty, dtz)
-__device__ __forceinline__ void rhs_tan(const Dyn& P, const float* x, const float* d, float s, float ds, float dtx,
-                                        float dty, float dtz, float* o) {
-  const float qw = x[3], qx = x[4], qy = x[5], qz = x[6], wx = x[10], wy = x[11], wz = x[12];
-  const float dqw = d[3], dqx = d[4], dqy = d[5], dqz = d[6], dwx = d[10], dwy = d[11], dwz = d[12];
+template <class R>
+__device__ __forceinline__ void rhs_tan(const DynT<R>& P, const R* x, const R* d, R s, R ds, R dtx, R dty, R dtz,
+                                        R* o) {
+  const R qw = x[3], qx = x[4], qy = x[5], qz = x[6], wx = x[10], wy = x[11], wz = x[12];
+  const R dqw = d[3], dqx = d[4], dqy = d[5], dqz = d[6], dwx = d[10], dwy = d[11], dwz = d[12];
   o[0] = d[7];
   o[1] = d[8];
   o[2] = d[9];
-  o[3] = 0.5f * (-(dqx * wx + qx * dwx) - (dqy * wy + qy * dwy) - (dqz * wz + qz * dwz));
-  o[4] = 0.5f * ((dqw * wx + qw * dwx) + (dqy * wz + qy * dwz) - (dqz * wy + qz * dwy));
-  o[5] = 0.5f * ((dqw * wy + qw * dwy) - (dqx * wz + qx * dwz) + (dqz * wx + qz * dwx));
-  o[6] = 0.5f * ((dqw * wz + qw * dwz) + (dqx * wy + qx * dwy) - (dqy * wx + qy * dwx));
-  const float b0 = 2.f * (qx * qz + qw * qy), b1 = 2.f * (qy * qz - qw * qx), b2 = 1.f - 2.f * (qx * qx + qy * qy);
-  const float db0 = 2.f * (dqx * qz + qx * dqz + dqw * qy + qw * dqy);
-  const float db1 = 2.f * (dqy * qz + qy * dqz - dqw * qx - qw * dqx);
-  const float db2 = -4.f * (qx * dqx + qy * dqy);
+  o[3] = R(0.5) * (-(dqx * wx + qx * dwx) - (dqy * wy + qy * dwy) - (dqz * wz + qz * dwz));
+  o[4] = R(0.5) * ((dqw * wx + qw * dwx) + (dqy * wz + qy * dwz) - (dqz * wy + qz * dwy));
+  o[5] = R(0.5) * ((dqw * wy + qw * dwy) - (dqx * wz + qx * dwz) + (dqz * wx + qz * dwx));
+  o[6] = R(0.5) * ((dqw * wz + qw * dwz) + (dqx * wy + qx * dwy) - (dqy * wx + qy * dwx));
+  const R b0 = R(2) * (qx * qz + qw * qy), b1 = R(2) * (qy * qz - qw * qx), b2 = R(1) - R(2) * (qx * qx + qy * qy);
+  const R db0 = R(2) * (dqx * qz + qx * dqz + dqw * qy + qw * dqy);
+  const R db1 = R(2) * (dqy * qz + qy * dqz - dqw * qx - qw * dqx);
+  const R db2 = R(-4) * (qx * dqx + qy * dqy);
   o[7] = ds * b0 + s * db0;
   o[8] = ds * b1 + s * db1;
   o[9] = ds * b2 + s * db2;
@@ -156,8 +189,9 @@ __device__ __forceinline__ void rhs_tan(const Dyn& P, const float* x, const floa
 }
 
 // one RK4 step x -> xn with the thrust held over the step
-__device__ __forceinline__ void rk4(const Dyn& P, const float* x, const float* u, float* xn) {
-  float s, tx, ty, tz, k[NX], acc[NX], xs[NX];
+template <class R>
+__device__ __forceinline__ void rk4(const DynT<R>& P, const R* x, const R* u, R* xn) {
+  R s, tx, ty, tz, k[NX], acc[NX], xs[NX];
   forces(P, u, s, tx, ty, tz);
   rhs(P, x, s, tx, ty, tz, k);
 #pragma unroll
@@ -168,13 +202,13 @@ __device__ __forceinline__ void rk4(const Dyn& P, const float* x, const float* u
   rhs(P, xs, s, tx, ty, tz, k);
 #pragma unroll
   for (int i = 0; i < NX; ++i) {
-    acc[i] += 2.f * k[i];
+    acc[i] += R(2) * k[i];
     xs[i] = x[i] + P.h2 * k[i];
   }
   rhs(P, xs, s, tx, ty, tz, k);
 #pragma unroll
   for (int i = 0; i < NX; ++i) {
-    acc[i] += 2.f * k[i];
+    acc[i] += R(2) * k[i];
     xs[i] = x[i] + P.h * k[i];
   }
   rhs(P, xs, s, tx, ty, tz, k);
@@ -183,32 +217,34 @@ __device__ __forceinline__ void rk4(const Dyn& P, const float* x, const float* u
 }
 
 // tangent direction owned by a lane: e_col for state columns, e_{col-13} for inputs
+template <class R>
 struct LaneDir {
-  float dx[NX];
-  float ds, dtx, dty, dtz;
+  R dx[NX];
+  R ds, dtx, dty, dtz;
 };
 
-__device__ __forceinline__ LaneDir make_dir(const Dyn& P, int col) {
-  LaneDir d;
+template <class R>
+__device__ __forceinline__ LaneDir<R> make_dir(const DynT<R>& P, int col) {
+  LaneDir<R> d;
 #pragma unroll
-  for (int i = 0; i < NX; ++i) d.dx[i] = (i == col) ? 1.f : 0.f;
+  for (int i = 0; i < NX; ++i) d.dx[i] = (i == col) ? R(1) : R(0);
   const int a = col - NX;
   const bool isu = col >= NX;
-  const float mx = (a == 0 || a == 1) ? 1.f : -1.f;
-  const float my = (a == 1 || a == 2) ? 1.f : -1.f;
-  const float mz = (a == 0 || a == 2) ? 1.f : -1.f;
-  d.ds = isu ? P.inv_m : 0.f;
-  d.dtx = isu ? P.arm_a * mx * P.iJx : 0.f;
-  d.dty = isu ? P.arm_a * my * P.iJy : 0.f;
-  d.dtz = isu ? P.kappa * mz * P.iJz : 0.f;
+  const R mx = (a == 0 || a == 1) ? R(1) : -R(1);
+  const R my = (a == 1 || a == 2) ? R(1) : -R(1);
+  const R mz = (a == 0 || a == 2) ? R(1) : -R(1);
+  d.ds = isu ? P.inv_m : R(0);
+  d.dtx = isu ? P.arm_a * mx * P.iJx : R(0);
+  d.dty = isu ? P.arm_a * my * P.iJy : R(0);
+  d.dtz = isu ? P.kappa * mz * P.iJz : R(0);
   return d;
 }
 
 // column of [A | B] = d f(x, u) / d(direction), by forward-mode differentiation
 // of the RK4 step (exact derivative of the discrete map)
-__device__ __forceinline__ void rk4_column(const Dyn& P, const float* x, const float* u, const LaneDir& D,
-                                           float* col) {
-  float s, tx, ty, tz, k[NX], dk[NX], acc[NX], dacc[NX], xs[NX], dxs[NX];
+template <class R>
+__device__ __forceinline__ void rk4_column(const DynT<R>& P, const R* x, const R* u, const LaneDir<R>& D, R* col) {
+  R s, tx, ty, tz, k[NX], dk[NX], acc[NX], dacc[NX], xs[NX], dxs[NX];
   forces(P, u, s, tx, ty, tz);
   rhs(P, x, s, tx, ty, tz, k);
   rhs_tan(P, x, D.dx, s, D.ds, D.dtx, D.dty, D.dtz, dk);
@@ -223,8 +259,8 @@ __device__ __forceinline__ void rk4_column(const Dyn& P, const float* x, const f
   rhs_tan(P, xs, dxs, s, D.ds, D.dtx, D.dty, D.dtz, dk);
 #pragma unroll
   for (int i = 0; i < NX; ++i) {
-    acc[i] += 2.f * k[i];
-    dacc[i] += 2.f * dk[i];
+    acc[i] += R(2) * k[i];
+    dacc[i] += R(2) * dk[i];
     xs[i] = x[i] + P.h2 * k[i];
     dxs[i] = D.dx[i] + P.h2 * dk[i];
   }
@@ -232,8 +268,8 @@ __device__ __forceinline__ void rk4_column(const Dyn& P, const float* x, const f
   rhs_tan(P, xs, dxs, s, D.ds, D.dtx, D.dty, D.dtz, dk);
 #pragma unroll
   for (int i = 0; i < NX; ++i) {
-    acc[i] += 2.f * k[i];
-    dacc[i] += 2.f * dk[i];
+    acc[i] += R(2) * k[i];
+    dacc[i] += R(2) * dk[i];
     xs[i] = x[i] + P.h * k[i];
     dxs[i] = D.dx[i] + P.h * dk[i];
   }

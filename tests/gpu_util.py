@@ -79,7 +79,7 @@ def describe(e):
 
 
 def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=True, grad_u=None, grad_x=None,
-            fp64_pivot=1e-6, ckpt=0, theta=False, tpar=False):
+            fp64_pivot=1e-6, ckpt=0, theta=False, tpar=False, f64=False, redo=False):
     import torch
 
     import paper_2605_29155_amd as D
@@ -90,6 +90,8 @@ def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=Tru
     tol = d["tol"] if tol is None else tol
     flags = (D.NEED_GRAD if need_grad else 0) | (D.PLAIN if plain else 0) | (D.LPT if lpt else 0)
     flags |= D.TPAR if tpar else 0
+    flags |= D.F64 if f64 else 0
+    flags |= D.F64_REDO if redo else 0
     cfg = D.make_config(B, Tm, d["cost_kind"], K, tol, flags, fp64_pivot, ckpt)
     t = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev) for k in ("x0", "Q", "p", "lo", "hi")}
     Tt = torch.from_numpy(d["T"].astype(np.int32)).to(dev)

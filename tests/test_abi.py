@@ -130,4 +130,20 @@ def test_time_parallel_workspace(D):
     assert plain > base
     assert 2 * 64 * 30 * 536 * 8 + 64 * 30 <= extra <= 2 * 64 * 30 * 536 * 8 + 64 * 30 + 2 * 256
     assert D.validate(D.make_config(4, 10, flags=D.TPAR | D.NEED_GRAD)) == 0
-    assert D.validate(D.make_config(4, 10, flags=0x20)) == -1
+    assert D.validate(D.make_config(4, 10, flags=0x80)) == -1
+    assert D.validate(D.make_config(4, 10, flags=D.F64_REDO)) == 0
+    assert D.validate(D.make_config(4, 10, flags=D.F64_REDO | D.F64)) == -1
+    assert D.validate(D.make_config(4, 10, flags=D.F64_REDO | D.PLAIN)) == -2
+    # the FP64 form runs as the persistent launch only
+    assert D.validate(D.make_config(4, 10, flags=D.F64)) == 0
+    assert D.validate(D.make_config(4, 10, flags=D.F64 | D.TPAR)) == -2
+    assert D.validate(D.make_config(4, 10, flags=D.F64 | D.PLAIN)) == -2
+
+
+def test_fp64_form_workspace(D):
+    """DMPC_F64 doubles the trajectory and gain regions of the workspace."""
+    for B, T in ((64, 20), (1000, 37)):
+        a = D.workspace_bytes(D.make_config(B, T))
+        b = D.workspace_bytes(D.make_config(B, T, flags=D.F64))
+        traj_gains = B * T * (5 * 20 + 68) * 4
+        assert abs((b - a) - traj_gains) <= 2 * 256  # regions are 256-byte aligned

@@ -115,3 +115,59 @@ def test_layer_autotune_first_call_then_reuse():
     assert (used.plain, used.waves_per_simd, used.grid_mode) == (got.plain, got.waves_per_simd, got.grid_mode)
     torch.cuda.synchronize()
     assert torch.equal(u1, u2)
+
+
+def test_tuned_choices_saved_and_loaded(tmp_path):
+    """Launch choices persist across handles through the tuning file, keyed by
+    the device's architecture: a new handle that loads the file launches the
+    stored choice; lines for another architecture, malformed lines and
+    out-of-range choices are skipped."""
+    import paper_2605_29155_amd as D
+    h = handle()
+    c1 = D.make_config(64, 12, 0, 3, 0.0, D.NEED_GRAD | D.TUNED)
+    c2 = D.make_config(128, 30, 1, 5, 1e-5, D.TUNED, ckpt_every=10)
+    D.set_tuned(h, c1, True, D.LaunchChoice(0, 1, 2, 1, 0.5))
+    D.set_tuned(h, c2, False, D.LaunchChoice(1, 0, 1, 0, 0.25))
+    path = tmp_path / "tuned.txt"
+    n = D.tuned_save(h, str(path))
+    assert n >= 2
+    lines = path.read_text().splitlines()
+    assert len(lines) == n and all(s.startswith("dmpc-tuned-v1 gfx950") for s in lines)
+    # another architecture, a malformed line and an out-of-range choice
+    arch, cu = lines[0].split()[1:3]
+    extra = ["dmpc-tuned-v1 gfx942 %s 64 12 0 1 0 1 0 0 2 0 0.1" % cu, "dmpc-tuned-v1 %s %s 1 2" % (arch, cu),
+             "dmpc-tuned-v1 %s %s 9 9 0 0 0 0 0 0 7 0 0.1" % (arch, cu)]
+    path.write_text("\n".join(lines + extra) + "\n")
+    h2 = D.Handle(0)
+    assert D.get_tuned(h2, c1, True) is None
+    assert D.tuned_load(h2, str(path)) == n
+    g1, g2 = D.get_tuned(h2, c1, True), D.get_tuned(h2, c2, False)
+    assert g1.as_dict() == dict(plain=0, lpt=1, waves_per_simd=2, grid_mode=1, ms=0.5)
+    assert g2.as_dict() == dict(plain=1, lpt=0, waves_per_simd=1, grid_mode=0, ms=0.25)
+    assert D.get_tuned(h2, D.make_config(9, 9), False) is None
+    with pytest.raises(D.DMPCError):
+        D.tuned_load(h2, str(tmp_path / "missing.txt"))
+
+
+def test_layer_tune_file_round_trip(tmp_path):
+    """A layer with a tune_file tunes a new shape once and writes the file; a
+    second layer built on that file starts with the choice and does not tune
+    again; both give the same solution."""
+    import torch
+
+    import paper_2605_29155_amd as D
+    d = W.make(1, B=64, T=12, seed=5100)
+    dev = "cuda:0"
+    path = str(tmp_path / "tuned.txt")
+    args = [torch.from_numpy(np.ascontiguousarray(d[k])).to(dev) for k in ("x0", "Q", "p", "lo", "hi")]
+    l1 = D.DMPCLayer(W.quad_params_f32(), max_iter=3, autotune=True, tune_file=path)
+    u1, _, _ = l1(*args)
+    cfg = l1.config(64, 12, need_grad=False)
+    c1 = D.get_tuned(l1.handle, cfg, False)
+    assert c1 is not None and (tmp_path / "tuned.txt").exists()
+    l2 = D.DMPCLayer(W.quad_params_f32(), max_iter=3, autotune=True, tune_file=path)
+    c2 = D.get_tuned(l2.handle, cfg, False)
+    assert c2 is not None and c2.as_dict() == c1.as_dict()
+    u2, _, _ = l2(*args)
+    torch.cuda.synchronize()
+    assert torch.equal(u1, u2)
