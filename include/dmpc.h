@@ -189,6 +189,32 @@ int dmpc_forward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, co
                  float* u_out, float* x_out, uint32_t* status, void* workspace, size_t workspace_bytes,
                  uint8_t* decision_log, void* stream);
 
+/* Size of the library's static workspace used by dmpc_forward_noalloc: one
+ * array of this many bytes in device memory on every device the library runs
+ * on, held until the process ends (64 MiB: a forward without DMPC_NEED_GRAD
+ * at B = 4096, T_max = 20 needs 55.2 MB, at B = 256, T_max = 50 8.6 MB). */
+#define DMPC_NOALLOC_WORKSPACE_BYTES (64u << 20)
+
+/* dmpc_forward without a caller workspace, for callers that cannot allocate
+ * device memory at the point of the call (code under HIP graph capture,
+ * control loops that forbid allocation).  Arguments and results as
+ * dmpc_forward, whose kernels it launches; the workspace is the library's
+ * static device array of DMPC_NOALLOC_WORKSPACE_BYTES on the handle's device.
+ * It allocates and frees nothing, and never synchronises.
+ * - cfg->flags must not hold DMPC_NEED_GRAD (DMPC_EINVAL): a backward would
+ *   read the workspace, which the next call overwrites.
+ * - A problem whose dmpc_workspace_bytes(cfg) exceeds
+ *   DMPC_NOALLOC_WORKSPACE_BYTES is DMPC_EUNSUPPORTED, with nothing launched.
+ * - Every call on one device shares that device's array: calls whose work
+ *   overlaps in time on one device (other streams, other handles, other host
+ *   threads) race and give undefined results.  Order them on one stream.
+ *   Nothing in the array is assumed to start at zero; the forward initialises
+ *   what it reads. */
+int dmpc_forward_noalloc(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* x0,
+                         const float* Q, const float* p, const float* u_lo, const float* u_hi, const int32_t* T,
+                         const float* u_init, float* u_out, float* x_out, uint32_t* status, uint8_t* decision_log,
+                         void* stream);
+
 /* Backward (Sec. IV after eq. (3)): given dL/du* [B][T_max][4] and
  * optionally dL/dx* [B][T_max][13] (NULL = zero), writes
  * grad_Q [B][T_max][17|153] (layout of Q; for the packed dense cost the

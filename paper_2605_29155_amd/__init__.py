@@ -69,6 +69,7 @@ def lib():
         L.dmpc_workspace_bytes.argtypes = [C.POINTER(Config)]
         L.dmpc_workspace_bytes.restype = sz
         L.dmpc_forward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 10 + [vp, sz, vp, vp]
+        L.dmpc_forward_noalloc.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 12
         L.dmpc_backward.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 5 + [sz] + [vp] * 6 + [vp]
         L.dmpc_last_launch_count.argtypes = [vp]
         L.dmpc_autotune.argtypes = [vp, C.POINTER(Config), QuadParams] + [vp] * 10 + [vp, sz, vp, C.POINTER(LaunchChoice)]
@@ -168,6 +169,20 @@ def forward_raw(h, cfg, params, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, w
                             _ptr(u_init), _ptr(u_out), _ptr(x_out), _ptr(status, "int32"), _ptr(ws, "uint8"),
                             ws.numel() if ws is not None else 0, _ptr(dlog, "uint8"), _stream(stream))
     h.check(rc, "dmpc_forward")
+
+
+NOALLOC_WORKSPACE_BYTES = 64 << 20  # DMPC_NOALLOC_WORKSPACE_BYTES
+
+
+def forward_noalloc(h, cfg, params, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, dlog=None, stream=None,
+                    u_init=None):
+    """dmpc_forward on the library's static workspace (no caller
+    workspace, nothing allocated); forward only, and calls on one device
+    must not overlap."""
+    rc = lib().dmpc_forward_noalloc(h._h, C.byref(cfg), params, _ptr(x0), _ptr(Q), _ptr(p), _ptr(u_lo), _ptr(u_hi),
+                                    _ptr(T, "int32"), _ptr(u_init), _ptr(u_out), _ptr(x_out), _ptr(status, "int32"),
+                                    _ptr(dlog, "uint8"), _stream(stream))
+    h.check(rc, "dmpc_forward_noalloc")
 
 
 def autotune(h, cfg, params, x0, Q, p, u_lo, u_hi, T, u_out, x_out, status, ws, stream=None, u_init=None):

@@ -15,6 +15,7 @@
 #include <array>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <vector>
 #include <cstdio>
 #include <cstring>
@@ -2070,13 +2071,24 @@ struct dmpc_handle_s {
   std::string arch;  // the device's architecture name (gcnArchName), keys saved launch choices
   int occ[2][2] = {{1, 1}, {1, 1}};  // resident workgroups per CU: [dense][waves-per-SIMD variant]
   int last_launches = 0;
+  void* scratch = nullptr;  // device address of this device's `scratch` array
   dmpc_launch_choice last_choice{};
   // launch choices found by dmpc_autotune (or set), per problem shape
   std::map<std::array<int, 6>, dmpc_launch_choice> tuned;
   std::string err;
 };
 
+// Workspace of dmpc_forward_noalloc: file-scope device memory, one copy on
+// every device the library is loaded on, held until the process ends.  Host
+// code never passes this name to a kernel or a copy (on the host it is only a
+// stand-in); it uses the device address hipGetSymbolAddress returns, looked
+// up once per device with that device current (scratch_address below).
+static __device__ __align__(256) unsigned char scratch[DMPC_NOALLOC_WORKSPACE_BYTES];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device -> address of that device's `scratch`
 
 int fail(dmpc_handle h, int code, const std::string& msg) {
   if (h) h->err = msg;
@@ -2087,6 +2099,21 @@ int fail(dmpc_handle h, int code, const std::string& msg) {
 int hip_check(dmpc_handle h, hipError_t e, const char* what) {
   if (e == hipSuccess) return DMPC_OK;
   return fail(h, DMPC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Address of `scratch` on `device`, which must be current.
+int scratch_address(dmpc_handle h, int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it == g_scratch_ptr.end()) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(h, DMPC_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    it = g_scratch_ptr.emplace(device, ptr).first;
+  }
+  *out = it->second;
+  return DMPC_OK;
 }
 
 // Makes a handle's device current for the life of the object and gives the
@@ -2361,6 +2388,7 @@ int dmpc_create(dmpc_handle* out, int device) {
   h->arch = prop.gcnArchName;
   DeviceScope scope(device);
   rc = hip_check(h, scope.status(), "hipSetDevice");
+  if (!rc) rc = scratch_address(h, device, &h->scratch);
   if (rc) {
     delete h;
     return rc;
@@ -2394,6 +2422,38 @@ int dmpc_forward(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, co
   KArgs A;
   int rc = forward_args(h, cfg, dyn, x0, Q, p, u_lo, u_hi, T, u_init, u_out, x_out, status, workspace,
                         workspace_bytes, decision_log, A);
+  if (rc || cfg->B == 0) return rc;
+  DeviceScope scope(h->device);
+  rc = hip_check(h, scope.status(), "hipSetDevice");
+  if (rc) return rc;
+  dmpc_launch_choice c = default_choice(cfg);
+  if (cfg->flags & DMPC_TUNED) {
+    auto it = h->tuned.find(shape_key(cfg, T != nullptr));
+    if (it != h->tuned.end()) c = it->second;
+  }
+  return launch_forward(h, cfg, A, T, c, (hipStream_t)stream);
+}
+
+int dmpc_forward_noalloc(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, const float* x0,
+                         const float* Q, const float* p, const float* u_lo, const float* u_hi, const int32_t* T,
+                         const float* u_init, float* u_out, float* x_out, uint32_t* status, uint8_t* decision_log,
+                         void* stream) {
+  if (!h) return fail(nullptr, DMPC_EINVAL, "NULL handle");
+  h->last_launches = 0;
+  int rc = check_cfg(cfg);
+  if (rc) return fail(h, rc, "invalid configuration");
+  if (cfg->flags & DMPC_NEED_GRAD)
+    return fail(h, DMPC_EINVAL,
+                "dmpc_forward_noalloc keeps no workspace for a backward: DMPC_NEED_GRAD needs dmpc_forward");
+  const size_t need = make_layout(cfg).total;
+  if (need > (size_t)DMPC_NOALLOC_WORKSPACE_BYTES)
+    return fail(h, DMPC_EUNSUPPORTED,
+                "dmpc_forward_noalloc: this problem needs " + std::to_string(need) +
+                    " bytes of workspace, more than the library's static " +
+                    std::to_string((size_t)DMPC_NOALLOC_WORKSPACE_BYTES) + " bytes; use dmpc_forward");
+  KArgs A;
+  rc = forward_args(h, cfg, dyn, x0, Q, p, u_lo, u_hi, T, u_init, u_out, x_out, status, h->scratch,
+                    (size_t)DMPC_NOALLOC_WORKSPACE_BYTES, decision_log, A);
   if (rc || cfg->B == 0) return rc;
   DeviceScope scope(h->device);
   rc = hip_check(h, scope.status(), "hipSetDevice");
