@@ -405,7 +405,8 @@ def cpu_baseline_leg(d, gpu, nsample=64):
     import oracle as orc
     import workloads as W
     sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from gpu_util import decision_agreement, maxabs, oracle_replay, rel, replay_violation, run_gpu
+    from gpu_util import (alpha_choices_valid, decision_agreement, maxabs, oracle_replay, pattern_agreement, rel,
+                          replay_violation, run_gpu)
     P = orc.params_from(W.quad_params_f32())
     avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     nthreads = max(1, min(16, avail))
@@ -459,7 +460,13 @@ def cpu_baseline_leg(d, gpu, nsample=64):
                dx0_rel_max=float(rel(sel(g["dx0"]), o["bwd"]["dx0"]).max()),
                grad_abs_max=float(max(maxabs(sel(g[k]), o["bwd"][k]).max() for k in ("dQ", "dp", "dx0"))),
                replayed_pattern_violation_max=float(replay_violation(o).max()),
-               decision_agreement=float(decision_agreement(g, o, idx)))
+               decision_agreement=float(decision_agreement(g, o, idx)),
+               pattern_agreement=float(pattern_agreement(o)),
+               alpha_choices_not_a_minimiser=int(alpha_choices_valid(o)),
+               decision_note="decision_agreement: every decision (step length, clamp patterns, iteration count) "
+                             "equal to a free FP64 oracle run's; pattern_agreement leaves out the step lengths, "
+                             "which tie to rounding once the steps are tiny; alpha_choices_not_a_minimiser counts "
+                             "kernel step lengths whose oracle cost is not within 1e-4 of the minimum")
     # the timed persistent run and the decision-logged run must agree exactly
     acc["bench_run_matches_logged_run"] = bool(np.array_equal(gpu["persistent"]["u"], g["u"]))
     u = gpu["persistent"]["u"]
@@ -627,6 +634,59 @@ def tune_survey():
     print("Kernel source hash %s." % kernel_source_hash(), flush=True)
 
 
+def oracle_table(budget=3.0):
+    """The FP64 oracle's time per workload on this host: forward on one thread
+    and on the host threads this process may use (at most 16), the
+    Riccati-adjoint backward and the dense-KKT backward (the verification
+    path), each on a bounded sample of the workload's instances (repeated for
+    about `budget` seconds) and scaled linearly to the batch (instances are
+    independent).  Test infrastructure only: nothing here runs on the GPU.
+    Prints one JSON line."""
+    import numpy as np
+
+    import oracle as orc
+    import workloads as W
+    P = orc.params_from(W.quad_params_f32())
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    nt = max(1, min(16, avail))
+    rows = []
+    for cid, n1, nall in ((0, 8, 8), (1, 64, 1024), (2, 64, 1024), (3, 64, 1024), (4, 32, 256)):
+        d = W.make(cid) if cid != 4 else W.make(4, B=nall)
+        B = W.CONFIGS[cid]["B"]
+
+        def sub(n):
+            return {k: d[k][:n] for k in ("x0", "Q", "p", "lo", "hi", "T", "grad_u")}
+
+        def timed(fn):
+            t0, reps = time.perf_counter(), 0
+            while True:
+                fn()
+                reps += 1
+                w = time.perf_counter() - t0
+                if w >= budget or reps >= 200:
+                    return w / reps
+
+        a1, aa = sub(n1), sub(min(nall, d["B"]))
+        fw = lambda a, t: orc.forward(P, a["x0"], a["Q"], a["p"], a["lo"], a["hi"], a["T"], K=d["K"], tol=d["tol"],
+                                      nthreads=t)  # noqa: E731
+        t1 = timed(lambda: fw(a1, 1)) / len(a1["T"])
+        ta = timed(lambda: fw(aa, nt)) / len(aa["T"])
+        f = fw(aa, nt)
+        bw = lambda m: orc.backward(P, aa["x0"], aa["Q"], aa["p"], aa["lo"], aa["hi"], f["u"], f["x"], aa["grad_u"],
+                                    T=aa["T"], method=m, nthreads=nt)  # noqa: E731
+        tr = timed(lambda: bw(0)) / len(aa["T"])
+        tk = timed(lambda: bw(1)) / len(aa["T"])
+        rows.append(dict(cfg=cid, B=B, T_max=d["T_max"], K=d["K"],
+                         fwd_1thread_s=t1 * B, fwd_all_s=ta * B, riccati_bwd_all_s=tr * B, dense_kkt_bwd_all_s=tk * B,
+                         fwd_bwd_solves_per_s_all=1.0 / (ta + tr),
+                         sample="forward on 1 thread: %d instances; the rest on %d threads: %d instances; per-instance "
+                                "times scaled to B=%d" % (n1, nt, len(aa["T"]), B)))
+        print("oracle cfg %d: fwd 1 thread %.3f s, fwd %d threads %.3f s, Riccati bwd %.3f s, dense-KKT bwd %.3f s "
+              "(scaled to B=%d)" % (cid, t1 * B, nt, ta * B, tr * B, tk * B, B), file=sys.stderr, flush=True)
+    print(json.dumps({"oracle_table": rows, "threads": nt, "host_cpu": cpu_model(), "host_nproc": os.cpu_count()}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -649,6 +709,9 @@ def main():
     ap.add_argument("--tune-survey", action="store_true",
                     help="forward time of every launch choice on the metric, ragged and dense workloads, and the "
                          "autotuner's pick; prints a markdown table")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="the FP64 oracle's forward (1 thread and all threads), Riccati-adjoint and dense-KKT "
+                         "backward times per workload on this host (CPU only); prints one JSON line")
     ap.add_argument("--profile-short", action="store_true",
                     help="for counter collection: two direct fwd+bwd calls of the persistent form, then a "
                          "256 MiB device copy whose FETCH_SIZE / WRITE_SIZE calibrate the HBM counters")
@@ -657,6 +720,9 @@ def main():
         print("bench.py runs on one GPU only: the instances are independent and the layer has no "
               "cross-GPU step; --gpus %d is not supported" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if a.oracle_table:
+        oracle_table()
+        return
     import torch
     dev = "cuda:0"
     if a.latency:
@@ -705,7 +771,7 @@ def main():
     else:
         form = ("persistent (autotuner: %d wave(s)/SIMD, grid mode %d, %s order), hipGraph fwd+bwd"
                 % (ch["waves_per_simd"], ch["grid_mode"], "longest-first" if ch["lpt"] else "queue"))
-        kname = "k_fwd_persistent<false, %d>" % ch["waves_per_simd"]
+        kname = "k_fwd_persistent<false, %d, float>" % ch["waves_per_simd"]
         traffic = load_traffic(kh, B) if ch["waves_per_simd"] == 1 else None
     print("bench: torch steps through DMPCLayer", file=sys.stderr, flush=True)
     ts = torch_steps(d, t)

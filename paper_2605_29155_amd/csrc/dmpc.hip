@@ -45,8 +45,6 @@ struct Ws {
   double* ck;   // [B][nck][CK_W] checkpoints of (V, v) at stages j * ckpt
   double* elem;  // [2][B][Tm][EL_W] time-parallel Riccati elements (ping-pong), or null
   uint8_t* pat;  // [B][Tm] clamp pattern of the last backward pass (time-parallel guess), or null
-  float* traj64;   // with DMPC_F64_REDO: the FP64 redo's trajectories [B][NSLOT][Tm][ZS] doubles, else null
-  float* gains64;  // with DMPC_F64_REDO: the FP64 redo's gains [B][Tm][GS] doubles, else null
 };
 
 struct KArgs {
@@ -73,6 +71,10 @@ struct KArgs {
   // its final nominal into (read by the backward)
   const int* redo_count;
   float* traj_f;
+  // with DMPC_F64_REDO: the redo's own trajectories [B][NSLOT][Tm][ZS] and
+  // gains [B][Tm][GS], doubles (else null)
+  float* traj64;
+  float* gains64;
 };
 
 struct Grp {
@@ -113,7 +115,12 @@ template <class R>
 struct V4 {
   R x, y, z, w;
 };
-__device__ __forceinline__ float4 ld4(const float* p) { return *(const float4*)p; }
+__device__ __forceinline__ const float4& ld4(const float* p) { return *(const float4*)p; }
+template <class R>
+__device__ __forceinline__ auto zero4() {
+  if constexpr (sizeof(R) == sizeof(float)) return make_float4(0.f, 0.f, 0.f, 0.f);
+  else return V4<double>{0.0, 0.0, 0.0, 0.0};
+}
 __device__ __forceinline__ V4<double> ld4(const double* p) {
   const double2 a = *(const double2*)p, c = *(const double2*)(p + 2);
   return {a.x, a.y, c.x, c.y};
@@ -390,10 +397,15 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     // wait also cover the loads issued after it.  The previous iteration's k
     // (the box-QP's warm start) is read at every iteration and ignored at the
     // first; at the last stage the "next" nominal is this stage's again.
-    decltype(ld4((const R*)nullptr)) s_kw = {R(0), R(0), R(0), R(0)};
+    auto s_kw = zero4<R>();
     if (MODE == 0) {
-      const auto w = ld4(gains_at<R>(A, b, t) + 64);
-      if (kit > 0) s_kw = w;
+      if constexpr (sizeof(R) == sizeof(float)) {
+        const float4 w = *(const float4*)(gains_at(A, b, t) + 64);
+        if (kit > 0) s_kw = w;
+      } else {
+        const auto w = ld4(gains_at<R>(A, b, t) + 64);
+        if (kit > 0) s_kw = w;
+      }
     }
     R zb[NZ];
 #pragma unroll
@@ -844,8 +856,13 @@ __global__ __launch_bounds__(64, OCC) void k_fwd_persistent(KArgs A) {
   const int lane = threadIdx.x, grp = lane >> 4, l = lane & 15;
   double* L = lds + grp * L_REG;
   // an FP64 redo takes the flagged instances listed in ws.order
-  const int nb = A.redo_count ? __builtin_amdgcn_readfirstlane(*A.redo_count) : A.B;
-  const int nq = (nb + 3) >> 2;
+  int nb = A.B, nq = A.nquads;
+  if constexpr (sizeof(R) == sizeof(double)) {
+    if (A.redo_count) {
+      nb = __builtin_amdgcn_readfirstlane(*A.redo_count);
+      nq = (nb + 3) >> 2;
+    }
+  }
   for (;;) {
     int q = 0;
     if (lane == 0) q = atomicAdd(A.ws.queue, 1);
@@ -2163,8 +2180,8 @@ KArgs base_args(const dmpc_config* c, void* workspace) {
   A.ws.ck = (double*)(w + L.ck);
   A.ws.elem = L.has_tpar ? (double*)(w + L.elem) : nullptr;
   A.ws.pat = L.has_tpar ? (uint8_t*)(w + L.pat) : nullptr;
-  A.ws.traj64 = L.has_redo ? (float*)(w + L.traj64) : nullptr;
-  A.ws.gains64 = L.has_redo ? (float*)(w + L.gains64) : nullptr;
+  A.traj64 = L.has_redo ? (float*)(w + L.traj64) : nullptr;
+  A.gains64 = L.has_redo ? (float*)(w + L.gains64) : nullptr;
   A.ckpt = c->ckpt_every;
   A.nck = L.nck;
   A.tstride = L.tstride;
@@ -2337,8 +2354,8 @@ int launch_forward(dmpc_handle h, const dmpc_config* cfg, KArgs A, const int32_t
       // FP32 launch no longer reads it) and the redo's counters sit in the
       // queue block, apart from the FP32 launch's counter
       KArgs Rd = A;
-      Rd.ws.traj = A.ws.traj64;
-      Rd.ws.gains = A.ws.gains64;
+      Rd.ws.traj = A.traj64;
+      Rd.ws.gains = A.gains64;
       Rd.ws.queue = A.ws.queue + 32;
       Rd.redo_count = A.ws.queue + 16;
       Rd.traj_f = A.ws.traj;

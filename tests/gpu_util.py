@@ -160,6 +160,21 @@ def decision_agreement(g, o, idx=None):
     return same.mean()
 
 
+def pattern_agreement(o):
+    """Fraction of instances whose free-run oracle takes the kernel's box-QP
+    clamp patterns at every stage of every iteration it ran and the same
+    number of iterations (the line-search choices left out: where the
+    candidates' costs tie to rounding, e.g. once the steps have become tiny,
+    the first minimiser is decided by rounding alone; alpha_choices_valid
+    checks those choices)."""
+    ff = o["free"]
+    same = ff["iters"] == o["iters"]
+    for b in range(len(same)):
+        k = o["iters"][b]
+        same[b] &= np.array_equal(ff["pattern"][b, :k], o["pattern"][b, :k])
+    return same.mean()
+
+
 def alpha_choices_valid(o, rtol=1e-4):
     """Every kernel line-search choice is a minimiser of the oracle's candidate
     costs up to rounding (the choice is a floating-point decision)."""
