@@ -28,11 +28,12 @@ sys.path.insert(0, ROOT)
 # box-QP, four-candidate line search; forward tail (linearise + fixed-mask
 # Riccati at the solution); adjoint sweeps; initial rollout.
 FLOP = dict(iter_stage=(27416, 30204), tail=(23478, 23478), adjoint=(1200, 2500), init=(593, 593))
-# MI355X vector peaks (256 CU x 4 SIMD x 16 lanes x 2 FLOP per FMA x 2.4 GHz = 78.6 TFLOP/s per FMA lane
-# op): the published FP32 figure, 157.3 TFLOP/s, counts packed FP32 (two FMAs per lane op); unpacked FP32
-# and FP64 FMAs issue at 78.6 TFLOP/s.  The headline fraction is against the published FP32 peak.
+# MI355X published vector peaks: FP32 157.3 TFLOP/s, FP64 78.6 TFLOP/s (bench.py --peaks measures 139 and
+# 75 with single FMAs, no packed FP32).  The headline fraction is against the FP32 peak; the fraction
+# against the FP64 peak is reported beside it, since a quarter of the forward's VALU instructions are FP64
+# FMAs.
 PEAK_FP32 = 157.3e12
-PEAK_UNPACKED = 78.6e12
+PEAK_FP64 = 78.6e12
 HBM_PEAK = 8.0e12
 
 
@@ -566,7 +567,7 @@ def config_lines(replays=20):
                 fl = Tb * (FLOP["init"][i] + its * FLOP["iter_stage"][i] + FLOP["tail"][i])
                 ach = fl.sum() / (ev_f["median"] * 1e-3)
                 row["roofline_fwd"] = dict(achieved=ach / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
-                                           frac=ach / PEAK_FP32, frac_vs_unpacked_78_6=ach / PEAK_UNPACKED,
+                                           frac=ach / PEAK_FP32, frac_vs_fp64_78_6=ach / PEAK_FP64,
                                            flop_fwd_total=float(fl.sum()),
                                            basis="per instance T_b (593 + k_b 27416 + 23478) diag / (593 + k_b "
                                                  "30204 + 23478) dense, k_b the iterations it used")
@@ -593,12 +594,16 @@ def tune_survey():
     import workloads as W
     dev = "cuda:0"
     h = D.Handle(0)
-    wl = ((2, "B=4096 T=20 diag (MLP cost)"), (3, "B=8192 T=10..50 ragged"), (4, "B=16384 T=50 dense, ckpt 10"))
-    print("| workload | form | waves/SIMD | grid | order | forward ms |")
-    print("|---|---|---|---|---|---|")
+    wl = ((2, "B=4096 T=20 diag (MLP cost)"), (3, "B=8192 T=10..50 ragged"), (4, "B=16384 T=50 dense, ckpt 10"),
+          (5, "B=256 T=50 hover-to-target"))
+    print("| workload | form | instances/wave | waves/SIMD | grid | order | forward ms |")
+    print("|---|---|---|---|---|---|---|")
     picks = []
     for cid, name in wl:
-        d = W.make(cid)
+        if cid == 5:
+            d = W.make_hover_target(256, 50)
+        else:
+            d = W.make(cid)
         t = _tensors(d, dev)
         S = _solver(h, d, t, D.NEED_GRAD | D.LPT | D.TUNED, dev)
         cands = [D.LaunchChoice(1, 0, 1, 0, 0.0)]
@@ -606,15 +611,19 @@ def tune_survey():
             for grid in (0, 1):
                 for lpt in (0, 1):
                     cands.append(D.LaunchChoice(0, lpt, occ, grid, 0.0))
+        for ipw in (2, 1):
+            for lpt in (0, 1):
+                cands.append(D.LaunchChoice(0, lpt, 1, 1, 0.0, ipw))
         for c in cands:
             D.set_tuned(h, S["cfg"], True, c)
             S["fwd"]()
             ms = min(event_times(S["fwd"], S["s"], 3))
             if c.plain:
-                print("| %s | per-launch | - | - | - | %.3f |" % (name, ms), flush=True)
+                print("| %s | per-launch | - | - | - | - | %.3f |" % (name, ms), flush=True)
             else:
-                print("| %s | persistent | %d | %s | %s | %.3f |"
-                      % (name, c.waves_per_simd, "one wave per unit" if c.grid_mode else "resident + queue",
+                print("| %s | persistent | %d | %d | %s | %s | %.3f |"
+                      % (name, c.inst_per_wave, c.waves_per_simd,
+                         "one wave per unit" if c.grid_mode else "resident + queue",
                          "longest first" if c.lpt else "queue", ms), flush=True)
         ch = S["tune"]()
         picks.append((name, ch))
@@ -627,8 +636,9 @@ def tune_survey():
         if ch["plain"]:
             print("- %s: per-launch form, %.3f ms" % (name, ch["ms"]))
         else:
-            print("- %s: persistent, %d wave(s)/SIMD, %s, %s, %.3f ms"
-                  % (name, ch["waves_per_simd"], "one wave per unit" if ch["grid_mode"] else "resident + queue",
+            print("- %s: persistent, %d instance(s)/wave, %d wave(s)/SIMD, %s, %s, %.3f ms"
+                  % (name, ch["inst_per_wave"], ch["waves_per_simd"],
+                     "one wave per unit" if ch["grid_mode"] else "resident + queue",
                      "longest horizon first" if ch["lpt"] else "queue order", ch["ms"]))
     print()
     print("Kernel source hash %s." % kernel_source_hash(), flush=True)
@@ -687,6 +697,52 @@ def oracle_table(budget=3.0):
           flush=True)
 
 
+def peaks(reps=20):
+    """Measured ceilings on this GPU: the FP32 (single, unpacked: packed FP32
+    is not built here) and FP64 FMA rates, every lane running eight
+    independent FMA chains, with the chip full (16 waves per SIMD) and with
+    one wave per SIMD (the forward kernel's occupancy at B = 4096); and the
+    rate of a float4 device copy of 1 GiB (bytes read + written).  Median of
+    `reps` launches, HIP events.  Prints one JSON line."""
+    import ctypes as C
+
+    import numpy as np
+    import torch
+
+    from paper_2605_29155_amd import build as _b
+    L = C.CDLL(_b.PEAKS_LIB)
+    L.peak_fma32.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    L.peak_fma64.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    L.peak_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+    dev = "cuda:0"
+    s = torch.cuda.Stream()
+    sp = C.c_void_p(s.cuda_stream)
+    out = {}
+    iters = 2048
+    cu = torch.cuda.get_device_properties(0).multi_processor_count
+    for occ, blocks, threads in (("full", cu * 16, 256), ("1wave_per_simd", cu * 4, 64),
+                                 ("2waves_per_simd", cu * 8, 64)):
+        for name, fn, dt in (("fma_f32", L.peak_fma32, torch.float32), ("fma_f64", L.peak_fma64, torch.float64)):
+            buf = torch.empty(blocks * threads, dtype=dt, device=dev)
+            run = lambda: fn(blocks, threads, iters, C.c_void_p(buf.data_ptr()), sp)  # noqa: E731
+            assert run() == 0
+            ms = float(np.median(event_times(run, s, reps)))
+            flop = 2.0 * 8 * 8 * iters * blocks * threads
+            out["%s_%s" % (name, occ)] = dict(tflops=flop / (ms * 1e-3) / 1e12, ms=ms, flop=flop, blocks=blocks,
+                                              threads=threads)
+    n4 = (1 << 30) // 16
+    src = torch.ones(n4 * 4, device=dev)
+    dst = torch.empty_like(src)
+    run = lambda: L.peak_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), n4, cu * 64, sp)  # noqa: E731
+    run()
+    ms = float(np.median(event_times(run, s, reps)))
+    out["copy"] = dict(gbps=2.0 * 16 * n4 / (ms * 1e-3) / 1e9, ms=ms, bytes=2 * 16 * n4)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    out["published"] = dict(fp32_tflops=157.3, fp64_tflops=78.6, hbm_gbps=8000.0)
+    print(json.dumps({"peaks": out, "compute_units": cu}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -709,6 +765,8 @@ def main():
     ap.add_argument("--tune-survey", action="store_true",
                     help="forward time of every launch choice on the metric, ragged and dense workloads, and the "
                          "autotuner's pick; prints a markdown table")
+    ap.add_argument("--peaks", action="store_true",
+                    help="measured unpacked-FP32 and FP64 FMA rates and device-copy bandwidth; one JSON line")
     ap.add_argument("--oracle-table", action="store_true",
                     help="the FP64 oracle's forward (1 thread and all threads), Riccati-adjoint and dense-KKT "
                          "backward times per workload on this host (CPU only); prints one JSON line")
@@ -735,6 +793,9 @@ def main():
         return
     if a.configs:
         config_lines()
+        return
+    if a.peaks:
+        peaks()
         return
     if a.tune_survey:
         tune_survey()
@@ -802,7 +863,7 @@ def main():
                      "kernel": kname, "kernel_ms": per["fwd_ms"],
                      "kernel_ms_is": "median HIP-event time of the forward call (queue reset + forward kernel) on "
                                      "the stream it is launched on, 20 calls after the timed region",
-                     "flop_per_solve_fwd": f_fwd, "frac_vs_unpacked_78_6": achieved / PEAK_UNPACKED},
+                     "flop_per_solve_fwd": f_fwd, "frac_vs_fp64_78_6": achieved / PEAK_FP64},
         "kernel_source_hash": kh,
     }
     if not a.no_cpu:

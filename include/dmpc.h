@@ -137,7 +137,7 @@ typedef struct {
   int32_t ckpt_every; /* 0: the forward stores every stage's factors for the backward (F_t, K_t and the
                          masked inverse of the free control block, 1424 bytes per stage).  c > 0: it
                          stores only V_t, v_t at t = c, 2c, ... (1584 bytes each) and dmpc_backward
-                         recomputes the factors segment by segment (twice) from those checkpoints;
+                         recomputes the factors segment by segment from those checkpoints;
                          the gradients are the same.  Checkpointing for long horizons. */
   float fp64_pivot;   /* pivot threshold below which a stage sets DMPC_ST_FP64; <= 0 disables */
   uint32_t flags;     /* DMPC_NEED_GRAD | DMPC_PLAIN | DMPC_LPT | DMPC_TUNED | DMPC_TPAR | DMPC_F64 |
@@ -157,6 +157,9 @@ typedef struct {
   int32_t grid_mode;      /* persistent: 0 = as many waves as fit at once, popping four-instance units
                              from a queue; 1 = one wave per four-instance unit */
   float ms;               /* dmpc_autotune: measured forward time of this choice (ms); else 0 */
+  int32_t inst_per_wave;  /* persistent: instances per wave, 4 (one per 16-lane row), or 2 / 1 with the
+                             other rows idle (one wave per SIMD), so that a small batch spreads over more
+                             SIMDs; the results are the same bits */
 } dmpc_launch_choice;
 
 typedef struct dmpc_handle_s* dmpc_handle;

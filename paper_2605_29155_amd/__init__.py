@@ -37,7 +37,10 @@ class Config(C.Structure):
 
 class LaunchChoice(C.Structure):
     _fields_ = [("plain", C.c_int32), ("lpt", C.c_int32), ("waves_per_simd", C.c_int32), ("grid_mode", C.c_int32),
-                ("ms", C.c_float)]
+                ("ms", C.c_float), ("inst_per_wave", C.c_int32)]
+
+    def __init__(self, plain=0, lpt=0, waves_per_simd=1, grid_mode=0, ms=0.0, inst_per_wave=4):
+        super().__init__(plain, lpt, waves_per_simd, grid_mode, ms, inst_per_wave)
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

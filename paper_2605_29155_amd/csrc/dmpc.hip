@@ -850,17 +850,20 @@ __device__ __forceinline__ void grp_write_state(const KArgs& A, const Grp& G, in
 // hide each other's latency when there are more waves than SIMDs).
 // R: precision of the dynamics, the linearisation, the line search and the
 // stored trajectories and gains (float; double in the FP64 form).
-template <bool DENSE, int OCC, class R = float>
+// IPW: instances per wave (4: one per 16-lane row; 2 or 1: the other rows
+// idle), so that a small batch spreads over more SIMDs and an instance does
+// not wait for the slowest of four in the box-QP's iterations.
+template <bool DENSE, int OCC, class R = float, int IPW = 4>
 __global__ __launch_bounds__(64, OCC) void k_fwd_persistent(KArgs A) {
   __shared__ double lds[4 * L_REG];
   const int lane = threadIdx.x, grp = lane >> 4, l = lane & 15;
   double* L = lds + grp * L_REG;
   // an FP64 redo takes the flagged instances listed in ws.order
-  int nb = A.B, nq = A.nquads;
+  int nb = A.B, nq = (IPW == 4) ? A.nquads : (A.B + IPW - 1) / IPW;
   if constexpr (sizeof(R) == sizeof(double)) {
     if (A.redo_count) {
       nb = __builtin_amdgcn_readfirstlane(*A.redo_count);
-      nq = (nb + 3) >> 2;
+      nq = (nb + IPW - 1) / IPW;
     }
   }
   for (;;) {
@@ -868,7 +871,7 @@ __global__ __launch_bounds__(64, OCC) void k_fwd_persistent(KArgs A) {
     if (lane == 0) q = atomicAdd(A.ws.queue, 1);
     q = __builtin_amdgcn_readfirstlane(q);
     if (q >= nq) break;
-    const Grp G = make_grp(A, q * 4 + grp, l, nb);
+    const Grp G = make_grp(A, (IPW == 4 || grp < IPW) ? q * IPW + grp : nb, l, nb);
     if (!G.valid) continue;
     uint32_t st = 0;
     int n = 0, iters = 0;
@@ -1914,7 +1917,9 @@ __global__ __launch_bounds__(64) void k_bwd(KArgs A) {
   FStage f0, f1;
   for (int sg = 0; sg < nseg; ++sg) {
     const int a = sg * seg, e = (a + seg < T) ? a + seg : T;
-    if (CKPT) recompute(a, e);
+    // the adjoint sweep above ended on the first segment, whose factors are
+    // still in the buffer
+    if (CKPT && sg > 0) recompute(a, e);
     fload(a, a, f0);
     __builtin_amdgcn_s_waitcnt(0);  // no load pending on loop entry
     for (int t = a; t < e; t += 2) {
@@ -2202,6 +2207,7 @@ dmpc_launch_choice default_choice(const dmpc_config* c) {
   d.lpt = (c->flags & DMPC_LPT) ? 1 : 0;
   d.waves_per_simd = 1;
   d.grid_mode = 0;
+  d.inst_per_wave = 4;
   d.ms = 0.f;
   return d;
 }
@@ -2262,8 +2268,10 @@ void launch_bwd(bool dense, bool ckpt, bool theta, int g, hipStream_t s, const K
 }
 
 template <bool DENSE, class R>
-void launch_persistent(int occ, int grid, hipStream_t s, const KArgs& A) {
-  if (occ == 2) k_fwd_persistent<DENSE, 2, R><<<grid, 64, 0, s>>>(A);
+void launch_persistent(int occ, int ipw, int grid, hipStream_t s, const KArgs& A) {
+  if (ipw == 1) k_fwd_persistent<DENSE, 1, R, 1><<<grid, 64, 0, s>>>(A);
+  else if (ipw == 2) k_fwd_persistent<DENSE, 1, R, 2><<<grid, 64, 0, s>>>(A);
+  else if (occ == 2) k_fwd_persistent<DENSE, 2, R><<<grid, 64, 0, s>>>(A);
   else k_fwd_persistent<DENSE, 1, R><<<grid, 64, 0, s>>>(A);
 }
 
@@ -2336,15 +2344,18 @@ int launch_forward(dmpc_handle h, const dmpc_config* cfg, KArgs A, const int32_t
     A.use_order = lpt ? 1 : 0;
     if (lpt) k_sort_by_T<<<1, 1024, 0, s>>>(T, cfg->B, cfg->T_max, A.ws.order, A.ws.queue);
     else k_reset_queue<<<1, 64, 0, s>>>(A.ws.queue);
-    const int occ = c.waves_per_simd == 2 ? 2 : 1;
+    // instances per wave: 4, or 2 / 1 with one wave per SIMD (registers uncapped)
+    const int ipw = (c.inst_per_wave == 1 || c.inst_per_wave == 2) ? c.inst_per_wave : 4;
+    const int occ = (ipw == 4 && c.waves_per_simd == 2) ? 2 : 1;
     const int cap = std::max(1, h->cu * h->occ[dense ? 1 : 0][occ - 1]);
-    const int grid = c.grid_mode == 1 ? nq : std::min(nq, cap);
+    const int units = (cfg->B + ipw - 1) / ipw;
+    const int grid = c.grid_mode == 1 ? units : std::min(units, cap);
     if (f64) {
-      if (dense) launch_persistent<true, double>(occ, grid, s, A);
-      else launch_persistent<false, double>(occ, grid, s, A);
+      if (dense) launch_persistent<true, double>(occ, ipw, grid, s, A);
+      else launch_persistent<false, double>(occ, ipw, grid, s, A);
     } else {
-      if (dense) launch_persistent<true, float>(occ, grid, s, A);
-      else launch_persistent<false, float>(occ, grid, s, A);
+      if (dense) launch_persistent<true, float>(occ, ipw, grid, s, A);
+      else launch_persistent<false, float>(occ, ipw, grid, s, A);
     }
     launches += 2;
     if (redo) {
@@ -2362,8 +2373,8 @@ int launch_forward(dmpc_handle h, const dmpc_config* cfg, KArgs A, const int32_t
       Rd.use_order = 1;
       k_reset_redo<<<1, 64, 0, s>>>(A.ws.queue + 16, A.ws.queue + 32);
       k_redo_list<<<(cfg->B + 255) / 256, 256, 0, s>>>(A.status, cfg->B, A.ws.order, A.ws.queue + 16);
-      if (dense) launch_persistent<true, double>(occ, grid, s, Rd);
-      else launch_persistent<false, double>(occ, grid, s, Rd);
+      if (dense) launch_persistent<true, double>(occ, ipw, grid, s, Rd);
+      else launch_persistent<false, double>(occ, ipw, grid, s, Rd);
       launches += 3;
     }
   }
@@ -2501,11 +2512,15 @@ int dmpc_autotune(dmpc_handle h, const dmpc_config* cfg, dmpc_quad_params dyn, c
     // workspace has room for it); persistent form x occupancy target x grid x order
     std::vector<dmpc_launch_choice> cand;
     const bool f64 = (cfg->flags & (DMPC_F64 | DMPC_F64_REDO)) != 0;
-    if (A.has_lin && !f64) cand.push_back(dmpc_launch_choice{1, 0, 1, 0, 0.f});
-    if (A.ws.elem && !f64) cand.push_back(dmpc_launch_choice{2, 0, 1, 0, 0.f});
+    if (A.has_lin && !f64) cand.push_back(dmpc_launch_choice{1, 0, 1, 0, 0.f, 4});
+    if (A.ws.elem && !f64) cand.push_back(dmpc_launch_choice{2, 0, 1, 0, 0.f, 4});
     for (int occ = 1; occ <= 2; ++occ)
       for (int grid = 0; grid <= 1; ++grid)
-        for (int lpt = 0; lpt <= (T ? 1 : 0); ++lpt) cand.push_back(dmpc_launch_choice{0, lpt, occ, grid, 0.f});
+        for (int lpt = 0; lpt <= (T ? 1 : 0); ++lpt) cand.push_back(dmpc_launch_choice{0, lpt, occ, grid, 0.f, 4});
+    // fewer instances per wave: worth trying only while the batch leaves SIMDs idle
+    if (cfg->B < 4 * h->cu * 4)
+      for (int ipw = 2; ipw >= 1; ipw /= 2)
+        for (int lpt = 0; lpt <= (T ? 1 : 0); ++lpt) cand.push_back(dmpc_launch_choice{0, lpt, 1, 1, 0.f, ipw});
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     rc = hip_check(h, hipEventCreate(&e0), "hipEventCreate");
@@ -2551,7 +2566,8 @@ int dmpc_set_tuned(dmpc_handle h, const dmpc_config* cfg, int has_T, const dmpc_
   int rc = check_cfg(cfg);
   if (rc) return fail(h, rc, "invalid configuration");
   if (choice->plain < 0 || choice->plain > 2 || choice->lpt < 0 || choice->lpt > 1 || choice->waves_per_simd < 1 ||
-      choice->waves_per_simd > 2 || choice->grid_mode < 0 || choice->grid_mode > 1)
+      choice->waves_per_simd > 2 || choice->grid_mode < 0 || choice->grid_mode > 1 ||
+      !(choice->inst_per_wave == 1 || choice->inst_per_wave == 2 || choice->inst_per_wave == 4))
     return fail(h, DMPC_EINVAL, "launch choice out of range");
   h->tuned[shape_key(cfg, has_T != 0)] = *choice;
   return DMPC_OK;
@@ -2577,7 +2593,8 @@ int dmpc_tuned_save(dmpc_handle h, const char* path) {
     const auto& c = kv.second;
     o << "dmpc-tuned-v1 " << h->arch << ' ' << h->cu;
     for (int v : k) o << ' ' << v;
-    o << ' ' << c.plain << ' ' << c.lpt << ' ' << c.waves_per_simd << ' ' << c.grid_mode << ' ' << c.ms << '\n';
+    o << ' ' << c.plain << ' ' << c.lpt << ' ' << c.waves_per_simd << ' ' << c.grid_mode << ' ' << c.ms << ' '
+      << c.inst_per_wave << '\n';
   }
   std::ofstream f(path, std::ios::trunc);
   if (!f) return fail(h, DMPC_EINVAL, std::string("cannot write ") + path);
@@ -2603,9 +2620,10 @@ int dmpc_tuned_load(dmpc_handle h, const char* path) {
     bool ok = true;
     for (int& v : k) ok = ok && (bool)(in >> v);
     ok = ok && (bool)(in >> c.plain >> c.lpt >> c.waves_per_simd >> c.grid_mode >> c.ms);
+    if (!(in >> c.inst_per_wave)) c.inst_per_wave = 4;  // lines written before this field existed
     if (!ok || arch != h->arch || cu != h->cu) continue;
     if (c.plain < 0 || c.plain > 2 || c.lpt < 0 || c.lpt > 1 || c.waves_per_simd < 1 || c.waves_per_simd > 2 ||
-        c.grid_mode < 0 || c.grid_mode > 1)
+        c.grid_mode < 0 || c.grid_mode > 1 || !(c.inst_per_wave == 1 || c.inst_per_wave == 2 || c.inst_per_wave == 4))
       continue;
     h->tuned[k] = c;
     ++n;

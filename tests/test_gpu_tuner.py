@@ -44,18 +44,21 @@ def test_every_persistent_choice_is_bitwise_identical():
     par = D.quad_params(W.quad_params_f32())
     t, o = _bufs(d, cfg, dev)
     ref = None
-    for occ in (1, 2):
-        for grid in (0, 1):
-            for lpt in (0, 1):
-                ch = D.LaunchChoice(0, lpt, occ, grid, 0.0)
-                D.set_tuned(h, cfg, True, ch)
-                r = _run(D, h, cfg, par, t, o)
-                used = D.last_launch_choice(h)
-                assert (used.plain, used.lpt, used.waves_per_simd, used.grid_mode) == (0, lpt, occ, grid)
-                if ref is None:
-                    ref = r
-                for k in r:
-                    assert np.array_equal(r[k], ref[k]), (occ, grid, lpt, k)
+    choices = [(occ, grid, lpt, 4) for occ in (1, 2) for grid in (0, 1) for lpt in (0, 1)]
+    # fewer instances per wave (96 is not a multiple of 4 times either, so the
+    # last unit is partly empty): the same bits
+    choices += [(1, grid, lpt, ipw) for ipw in (2, 1) for grid in (0, 1) for lpt in (0, 1)]
+    for occ, grid, lpt, ipw in choices:
+        ch = D.LaunchChoice(0, lpt, occ, grid, 0.0, ipw)
+        D.set_tuned(h, cfg, True, ch)
+        r = _run(D, h, cfg, par, t, o)
+        used = D.last_launch_choice(h)
+        assert (used.plain, used.lpt, used.waves_per_simd, used.grid_mode, used.inst_per_wave) == \
+            (0, lpt, occ, grid, ipw)
+        if ref is None:
+            ref = r
+        for k in r:
+            assert np.array_equal(r[k], ref[k]), (occ, grid, lpt, ipw, k)
     # the per-launch form agrees to rounding
     D.set_tuned(h, cfg, True, D.LaunchChoice(1, 0, 1, 0, 0.0))
     r = _run(D, h, cfg, par, t, o)
@@ -126,11 +129,13 @@ def test_tuned_choices_saved_and_loaded(tmp_path):
     h = handle()
     c1 = D.make_config(64, 12, 0, 3, 0.0, D.NEED_GRAD | D.TUNED)
     c2 = D.make_config(128, 30, 1, 5, 1e-5, D.TUNED, ckpt_every=10)
+    c3 = D.make_config(32, 50, 0, 5, 0.0, D.TUNED)
     D.set_tuned(h, c1, True, D.LaunchChoice(0, 1, 2, 1, 0.5))
     D.set_tuned(h, c2, False, D.LaunchChoice(1, 0, 1, 0, 0.25))
+    D.set_tuned(h, c3, False, D.LaunchChoice(0, 0, 1, 1, 0.125, 1))
     path = tmp_path / "tuned.txt"
     n = D.tuned_save(h, str(path))
-    assert n >= 2
+    assert n >= 3
     lines = path.read_text().splitlines()
     assert len(lines) == n and all(s.startswith("dmpc-tuned-v1 gfx950") for s in lines)
     # another architecture, a malformed line and an out-of-range choice
@@ -142,9 +147,15 @@ def test_tuned_choices_saved_and_loaded(tmp_path):
     assert D.get_tuned(h2, c1, True) is None
     assert D.tuned_load(h2, str(path)) == n
     g1, g2 = D.get_tuned(h2, c1, True), D.get_tuned(h2, c2, False)
-    assert g1.as_dict() == dict(plain=0, lpt=1, waves_per_simd=2, grid_mode=1, ms=0.5)
-    assert g2.as_dict() == dict(plain=1, lpt=0, waves_per_simd=1, grid_mode=0, ms=0.25)
+    assert g1.as_dict() == dict(plain=0, lpt=1, waves_per_simd=2, grid_mode=1, ms=0.5, inst_per_wave=4)
+    assert g2.as_dict() == dict(plain=1, lpt=0, waves_per_simd=1, grid_mode=0, ms=0.25, inst_per_wave=4)
+    assert D.get_tuned(h2, c3, False).inst_per_wave == 1
     assert D.get_tuned(h2, D.make_config(9, 9), False) is None
+    # a line without the instances-per-wave field (the earlier format) reads as 4
+    old = [ln for ln in lines if ln.split()[3:9] == ["64", "12", "0", "1", "0", "1"]][0]
+    path.write_text(" ".join(old.split()[:-1]) + "\n")
+    h3 = D.Handle(0)
+    assert D.tuned_load(h3, str(path)) == 1 and D.get_tuned(h3, c1, True).inst_per_wave == 4
     with pytest.raises(D.DMPCError):
         D.tuned_load(h2, str(tmp_path / "missing.txt"))
 
