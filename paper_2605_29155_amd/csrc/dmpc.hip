@@ -359,7 +359,12 @@ template <int N, class F>
 __device__ __forceinline__ void sfor(F&& f) {
   sfor_impl(std::make_integer_sequence<int, N>{}, f);
 }
-template <bool DENSE, int MODE, bool LIN_INLINE, class R = float>
+// LOWREG: for a kernel capped at 256 registers (two waves per SIMD): the
+// symmetric V is written with masked stores from two bases, and the lane and
+// column indices are made opaque at each stage so that the compiler recomputes
+// the addresses and masks derived from them instead of holding them (or
+// spilling them) across the stages.  Same operations, same results.
+template <bool DENSE, int MODE, bool LIN_INLINE, class R = float, bool LOWREG = false>
 __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* L, uint32_t& st, int t_hi,
                           int t_lo = 0, const double* vinit = nullptr, int tbase = 0) {
   const int l = G.l, col = G.col, b = G.b, T = G.T;
@@ -481,9 +486,14 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
       } else {
         const float* crow = A.Q + srow * NPK;
         double gc = (double)prow[col], gz = (double)prow[0];
+        // with LOWREG the column index is made opaque to the compiler at each
+        // stage, so that it recomputes the 17 packed offsets here instead of
+        // holding them across the stages
+        int cl = col;
+        if (LOWREG) asm volatile("" : "+v"(cl));
 #pragma unroll
         for (int i = 0; i < NZ; ++i) {
-          const double cc = (double)crow[i <= col ? pidx(i, col) : pidx(col, i)];
+          const double cc = (double)crow[i <= cl ? pidx(i, cl) : pidx(cl, i)];
           Qc[i] += cc;
           gc = fma(cc, (double)zb[i], gc);
           gz = fma((double)crow[i], (double)zb[i], gz);
@@ -591,14 +601,30 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
       for (int j = 0; j < NX; ++j) S[j] = (l == 0) ? R0r[j] : Sq[j];
 #pragma unroll
       for (int a = 0; a < 4; ++a) v_block(S, Kd[a], Qux[a]);
-      sfor<NX>([&](auto J) {
-        constexpr int j = J;
-        const double s = S[j];
-        const int a1 = (j >= l) ? (L_V + l * 14 + j) : (L_DUM + l);
-        const int a2 = (j > l) ? (L_V + j * 14 + l) : (L_DUM + l);
-        L[a1] = s;
-        L[a2] = s;
-      });
+      if (LOWREG) {
+        // masked stores from two bases (row l, column l) with constant
+        // offsets: no per-entry address is held across the stages
+        // (the lane index made opaque at each stage: the masks and bases are
+        // recomputed here rather than held across the stages)
+        int lv = l;
+        asm volatile("" : "+v"(lv));
+        double* row = L + L_V + lv * 14;
+        double* colm = L + L_V + lv;
+        sfor<NX>([&](auto J) {
+          constexpr int j = J;
+          if (j >= lv) row[j] = S[j];
+          if (j > lv) colm[j * 14] = S[j];
+        });
+      } else {
+        sfor<NX>([&](auto J) {
+          constexpr int j = J;
+          const double s = S[j];
+          const int a1 = (j >= l) ? (L_V + l * 14 + j) : (L_DUM + l);
+          const int a2 = (j > l) ? (L_V + j * 14 + l) : (L_DUM + l);
+          L[a1] = s;
+          L[a2] = s;
+        });
+      }
       vl = vi;
     }
     lds_sync();
@@ -881,7 +907,7 @@ __global__ __launch_bounds__(64, OCC) void k_fwd_persistent(KArgs A) {
       bool done = false;
       for (int k = 0; k < A.K; ++k) {
         if (done) continue;
-        grp_sweep<DENSE, 0, true, R>(A, G, n, k, L, st, G.T);
+        grp_sweep<DENSE, 0, true, R, OCC == 2>(A, G, n, k, L, st, G.T);
         mem_fence_wg();
         R J, dm, dsel;
         grp_ls<DENSE, R>(A, G, n, J, dm);
@@ -901,8 +927,8 @@ __global__ __launch_bounds__(64, OCC) void k_fwd_persistent(KArgs A) {
       }
       if (A.tol > 0.f && !(st & ST_CONVERGED)) st |= ST_MAXITER;
       if (A.need_grad) {
-        if (A.ckpt > 0) grp_sweep<DENSE, 2, true, R>(A, G, n, 0, L, st, G.T);
-        else grp_sweep<DENSE, 1, true, R>(A, G, n, 0, L, st, G.T);
+        if (A.ckpt > 0) grp_sweep<DENSE, 2, true, R, OCC == 2>(A, G, n, 0, L, st, G.T);
+        else grp_sweep<DENSE, 1, true, R, OCC == 2>(A, G, n, 0, L, st, G.T);
       }
     }
     grp_outputs<R>(A, G, n);

@@ -35,12 +35,13 @@ def _run(D, h, cfg, par, t, o):
     return {k: o[k].cpu().numpy().copy() for k in ("u", "x", "st", "dl", "gQ", "gp", "gx0")}
 
 
-def test_every_persistent_choice_is_bitwise_identical():
+@pytest.mark.parametrize("cfg_id", [3, 4], ids=["ragged-diag", "dense"])
+def test_every_persistent_choice_is_bitwise_identical(cfg_id):
     import paper_2605_29155_amd as D
-    d = W.make(3, B=96, T=20, seed=5003)
+    d = W.make(cfg_id, B=96, T=20, seed=5003)
     dev = "cuda:0"
     h = handle()
-    cfg = D.make_config(96, 20, 0, 4, 1e-5, D.NEED_GRAD | D.TUNED)
+    cfg = D.make_config(96, 20, d["cost_kind"], 4, 1e-5 if cfg_id == 3 else 0.0, D.NEED_GRAD | D.TUNED)
     par = D.quad_params(W.quad_params_f32())
     t, o = _bufs(d, cfg, dev)
     ref = None
