@@ -377,13 +377,17 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
   if (t_hi > t_lo) load_z(traj_at<R>(A, b, n, t_hi - 1), zn);
   __builtin_amdgcn_s_waitcnt(0);  // no load pending on loop entry (see grp_ls)
   for (int t = t_hi - 1; t >= t_lo; --t) {
+    // LOWREG: this stage's copies of the lane and column indices, opaque to the
+    // compiler, so that what it derives from them is recomputed per stage
+    int l_s = l, col_s = col;
+    if (LOWREG) asm volatile("" : "+v"(l_s), "+v"(col_s));
     if (MODE == 2 && t + 1 < T && (t + 1) % A.ckpt == 0) {
       // V, v of stage t + 1 (complete since the last row sync): exact FP64 image
       double* ck = A.ws.ck + ((size_t)b * A.nck + ((t + 1) / A.ckpt - 1)) * CK_W;
-      if (l < NX) {
+      if (l_s < NX) {
 #pragma unroll
-        for (int j = 0; j < NX; ++j) ck[l * 14 + j] = Vr[j];
-        ck[CK_VV + l] = vl;
+        for (int j = 0; j < NX; ++j) ck[l_s * 14 + j] = Vr[j];
+        ck[CK_VV + l_s] = vl;
       }
     }
     const R* zp = traj_at<R>(A, b, n, t);
@@ -391,10 +395,10 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     // vector-memory counter is in order, so they can then be waited for
     // without also waiting for the prefetch
     const size_t srow0 = (size_t)b * A.Tm + t;
-    const R s_zc = zp[col < NX ? col : col + 3];
-    const float s_qc = DENSE ? 0.f : A.Q[srow0 * NZ + col];
+    const R s_zc = zp[col_s < NX ? col_s : col_s + 3];
+    const float s_qc = DENSE ? 0.f : A.Q[srow0 * NZ + col_s];
     const float s_q0 = DENSE ? 0.f : A.Q[srow0 * NZ];
-    const float s_pc = A.p[srow0 * NZ + col];
+    const float s_pc = A.p[srow0 * NZ + col_s];
     const float s_p0 = A.p[srow0 * NZ];
     // No branch around these loads (nor around the stores at the end of the
     // stage): the wait-count insertion assumes the fewest operations in flight
@@ -420,10 +424,10 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     R Fc[NX];
     if (has_dyn) {
       if (LIN_INLINE) {
-        const LaneDir<R> D = make_dir(dyn_of<R>(A), col);
+        const LaneDir<R> D = make_dir(dyn_of<R>(A), col_s);
         rk4_column(dyn_of<R>(A), zb, zb + NX, D, Fc);
       } else {
-        const float* fp = lin_at(A, b, t) + col * 16;
+        const float* fp = lin_at(A, b, t) + col_s * 16;
 #pragma unroll
         for (int k = 0; k < NX; ++k) Fc[k] = fp[k];
       }
@@ -433,12 +437,12 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     }
     if (MODE == 1) {
       float* tp = tail_at(A, b, t - tbase);
-      float* fc = tp + col * 16;
+      float* fc = tp + col_s * 16;
       *(float4*)(fc) = make_float4((float)Fc[0], (float)Fc[1], (float)Fc[2], (float)Fc[3]);
       *(float4*)(fc + 4) = make_float4((float)Fc[4], (float)Fc[5], (float)Fc[6], (float)Fc[7]);
       *(float4*)(fc + 8) = make_float4((float)Fc[8], (float)Fc[9], (float)Fc[10], (float)Fc[11]);
       fc[12] = (float)Fc[12];
-      if (l == NX) {  // column 0 = e_0 (zero at the last stage)
+      if (l_s == NX) {  // column 0 = e_0 (zero at the last stage)
         const float e = has_dyn ? 1.f : 0.f;
         *(float4*)(tp) = make_float4(e, 0.f, 0.f, 0.f);
         *(float4*)(tp + 4) = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -485,15 +489,10 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
         qdiag = qd_c;
       } else {
         const float* crow = A.Q + srow * NPK;
-        double gc = (double)prow[col], gz = (double)prow[0];
-        // with LOWREG the column index is made opaque to the compiler at each
-        // stage, so that it recomputes the 17 packed offsets here instead of
-        // holding them across the stages
-        int cl = col;
-        if (LOWREG) asm volatile("" : "+v"(cl));
+        double gc = (double)prow[col_s], gz = (double)prow[0];
 #pragma unroll
         for (int i = 0; i < NZ; ++i) {
-          const double cc = (double)crow[i <= cl ? pidx(i, cl) : pidx(cl, i)];
+          const double cc = (double)crow[i <= col_s ? pidx(i, col_s) : pidx(col_s, i)];
           Qc[i] += cc;
           gc = fma(cc, (double)zb[i], gc);
           gz = fma((double)crow[i], (double)zb[i], gz);
@@ -529,10 +528,10 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
           H[bb * 4 + a] = h[m];
         }
     }
-    lds_write<NX>(L + L_QX + l * 14, Qc);
+    lds_write<NX>(L + L_QX + l_s * 14, Qc);
     // this lane's diagonal entry of the block, read now and completed with the
     // diagonal cost after the box-QP (the read's latency then hides behind it)
-    const double qdd = DENSE ? 0.0 : L[L_QX + l * 15];
+    const double qdd = DENSE ? 0.0 : L[L_QX + l_s * 15];
     // Y[0, :] by lane (row 0 of Q without the cost), broadcast only after the
     // box-QP so that its 32 registers are free during the QP
     double y0b[16];
@@ -563,17 +562,17 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     }
     // every lane writes its diagonal entry back (row 0 and rows 13..15 are not
     // read below); then the rows of Q are read ahead of their use
-    if (!DENSE) L[L_QX + l * 15] = qdd + qdiag;
+    if (!DENSE) L[L_QX + l_s * 15] = qdd + qdiag;
     double Sq[NX];
 #pragma unroll
-    for (int j = 0; j < NX; ++j) Sq[j] = L[L_QX + l * 14 + j];
+    for (int j = 0; j < NX; ++j) Sq[j] = L[L_QX + l_s * 14 + j];
 
     bcast16(y0b, Yc[0]);
     // gain column: K[:, l] = -Qff^{-1} Q_ux[:, l] on the free rows, 0 on clamped rows
     double Qux[4], Kd[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      Qux[a] = (l == 0) ? R0(NX + a) : Qc[NX + a];
+      Qux[a] = (l_s == 0) ? R0(NX + a) : Qc[NX + a];
       Kd[a] = fr[a] * Qux[a];
     }
     solve4(C, Kd);
@@ -592,35 +591,31 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     double R0r[NX];
 #pragma unroll
     for (int j = 0; j < NX; ++j) R0r[j] = (j == 0) ? v00 + c00 : R0(j);
-    if (l < NX) {
-      double vi = (l == 0) ? q0 : qc;
+    if (l_s < NX) {
+      double vi = (l_s == 0) ? q0 : qc;
 #pragma unroll
       for (int a = 0; a < 4; ++a) vi = fma(Qux[a], kv[a], vi);
       double S[NX];
 #pragma unroll
-      for (int j = 0; j < NX; ++j) S[j] = (l == 0) ? R0r[j] : Sq[j];
+      for (int j = 0; j < NX; ++j) S[j] = (l_s == 0) ? R0r[j] : Sq[j];
 #pragma unroll
       for (int a = 0; a < 4; ++a) v_block(S, Kd[a], Qux[a]);
       if (LOWREG) {
         // masked stores from two bases (row l, column l) with constant
         // offsets: no per-entry address is held across the stages
-        // (the lane index made opaque at each stage: the masks and bases are
-        // recomputed here rather than held across the stages)
-        int lv = l;
-        asm volatile("" : "+v"(lv));
-        double* row = L + L_V + lv * 14;
-        double* colm = L + L_V + lv;
+        double* row = L + L_V + l_s * 14;
+        double* colm = L + L_V + l_s;
         sfor<NX>([&](auto J) {
           constexpr int j = J;
-          if (j >= lv) row[j] = S[j];
-          if (j > lv) colm[j * 14] = S[j];
+          if (j >= l_s) row[j] = S[j];
+          if (j > l_s) colm[j * 14] = S[j];
         });
       } else {
         sfor<NX>([&](auto J) {
           constexpr int j = J;
           const double s = S[j];
-          const int a1 = (j >= l) ? (L_V + l * 14 + j) : (L_DUM + l);
-          const int a2 = (j > l) ? (L_V + j * 14 + l) : (L_DUM + l);
+          const int a1 = (j >= l_s) ? (L_V + l_s * 14 + j) : (L_DUM + l_s);
+          const int a2 = (j > l_s) ? (L_V + j * 14 + l_s) : (L_DUM + l_s);
           L[a1] = s;
           L[a2] = s;
         });
@@ -628,16 +623,16 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
       vl = vi;
     }
     lds_sync();
-    if (l < NX) lds_read<NX>(L + L_V + l * 14, Vr);
+    if (l_s < NX) lds_read<NX>(L + L_V + l_s * 14, Vr);
 
     if (MODE == 0) {
       // no branch around the stores (see the loads at the top of the stage):
       // lanes 13..15 fill the unused padding of the gain rows, and every lane
       // writes the same k
 #pragma unroll
-      for (int a = 0; a < 4; ++a) gp[a * 16 + l] = Kc[a];
+      for (int a = 0; a < 4; ++a) gp[a * 16 + l_s] = Kc[a];
       st4(gp + 64, (R)kv[0], (R)kv[1], (R)kv[2], (R)kv[3]);
-      if ((A.dlog || A.ws.pat) && l == 0) {
+      if ((A.dlog || A.ws.pat) && l_s == 0) {
         unsigned code = 0;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
@@ -649,9 +644,9 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
       }
     } else if (MODE == 1) {
       float* tp = tail_at(A, b, t - tbase);
-      if (l < NX) *(float4*)(tp + FS + l * 4) = make_float4((float)Kc[0], (float)Kc[1], (float)Kc[2], (float)Kc[3]);
+      if (l_s < NX) *(float4*)(tp + FS + l_s * 4) = make_float4((float)Kc[0], (float)Kc[1], (float)Kc[2], (float)Kc[3]);
       // M = masked inverse of the free block (zero rows/columns on clamped controls), FP64
-      if (l == NX + 1) {
+      if (l_s == NX + 1) {
         double M[16];
 #pragma unroll
         for (int bb = 0; bb < 4; ++bb) {
