@@ -832,8 +832,9 @@ def main():
     else:
         form = ("persistent (autotuner: %d wave(s)/SIMD, grid mode %d, %s order), hipGraph fwd+bwd"
                 % (ch["waves_per_simd"], ch["grid_mode"], "longest-first" if ch["lpt"] else "queue"))
-        kname = "k_fwd_persistent<false, %d, float>" % ch["waves_per_simd"]
-        traffic = load_traffic(kh, B) if ch["waves_per_simd"] == 1 else None
+        ipw = ch.get("inst_per_wave", 4)
+        kname = "k_fwd_persistent<false, %d, float, %d>" % (ch["waves_per_simd"], ipw)
+        traffic = load_traffic(kh, B) if (ch["waves_per_simd"], ipw) == (1, 4) else None
     print("bench: torch steps through DMPCLayer", file=sys.stderr, flush=True)
     ts = torch_steps(d, t)
     import numpy as np
