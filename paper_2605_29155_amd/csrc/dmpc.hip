@@ -554,7 +554,7 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     if (MODE == 0) {
       double kw[4] = {0.0, 0.0, 0.0, 0.0};
       kw[0] = s_kw.x; kw[1] = s_kw.y; kw[2] = s_kw.z; kw[3] = s_kw.w;
-      boxqp(H, qu, dl, dh, kw, A.piv, kv, fr, C, st);
+      boxqp_row(H, qu, dl, dh, kw, A.piv, (int)(__lane_id() & 48u), l_s, kv, fr, C, st);
     } else {
 #pragma unroll
       for (int a = 0; a < 4; ++a) fr[a] = (zb[NX + a] == G.lo[a] || zb[NX + a] == G.hi[a]) ? 0.0 : 1.0;

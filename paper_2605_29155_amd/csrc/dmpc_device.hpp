@@ -488,4 +488,80 @@ __device__ __forceinline__ void boxqp(const double* H, const double* q, const do
   }
 }
 
+
+// value of v in the lane whose byte address (4 x lane) is addr
+__device__ __forceinline__ double lane_read(int addr, double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The same stagewise box-QP, solved by the 16 lanes of an instance's row at
+// once (every lane holds H, q and the bounds).  A coordinate that ends on a
+// bound ends on the bound its gradient at the clamped warm start points to
+// (descent lowers it: lower bound, else upper) in nearly every stage, so the
+// 16 free/clamped subsets with those sides cover the solution: lane j takes
+// the coordinates of the set bits of j as free, solves the face problem for
+// the free ones with the others on their bounds, and checks the optimality
+// conditions (free coordinates inside the box, clamped ones with correctly
+// signed multipliers).  For H > 0 the minimiser is unique, so the valid lanes
+// agree; the row takes the lowest one's step, free mask, factor and flags.
+// When no lane is valid the row runs the active-set method (boxqp) instead.
+// One pass replaces the active-set iterations, whose count varies between
+// the four instances of a wave.  row0: the row's first lane in the wave;
+// j: the lane's index within the row.  All 16 lanes of the row must be active.
+__device__ __forceinline__ void boxqp_row(const double* H, const double* q, const double* lo, const double* hi,
+                                          const double* xw, float piv, int row0, int j, double* x, double* fr,
+                                          Fact4& C, uint32_t& st) {
+  double x0[4], g0[4], xc[4], frl[4], r[4];
+  bool fixed[4], onlo[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) x0[a] = clampd(xw[a], lo[a], hi[a]);
+  qp_grad(H, q, x0, g0);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    fixed[a] = !(lo[a] < hi[a]);
+    onlo[a] = g0[a] > 0.0;
+    frl[a] = (!fixed[a] && ((j >> a) & 1)) ? 1.0 : 0.0;
+    xc[a] = fixed[a] ? x0[a] : (onlo[a] ? lo[a] : hi[a]);
+  }
+  // right-hand side of the free block: -(q_F + H_FC x_C)
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double s = q[a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) s = fma(H[a * 4 + b], (1.0 - frl[b]) * xc[b], s);
+    r[a] = -frl[a] * s;
+  }
+  uint32_t stl = 0;
+  Fact4 Cl;
+  ldl4(H, frl, piv, Cl, stl);
+  solve4(Cl, r);
+  double xl[4], g[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) xl[a] = frl[a] != 0.0 ? r[a] : xc[a];
+  qp_grad(H, q, xl, g);
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    if (fixed[a]) ok = ok && !((j >> a) & 1);  // a fixed coordinate is never free
+    else if (frl[a] != 0.0) ok = ok && xl[a] >= lo[a] && xl[a] <= hi[a];
+    else ok = ok && (onlo[a] ? g[a] >= 0.0 : g[a] <= 0.0);
+  }
+  const unsigned rm = (unsigned)(__ballot(ok) >> row0) & 0xffffu;
+  const int src = rm ? __builtin_ctz(rm) : 0;
+  const int addr = (row0 + src) * 4;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) x[a] = lane_read(addr, xl[a]);
+#pragma unroll
+  for (int i = 0; i < 10; ++i) C.L[i] = lane_read(addr, Cl.L[i]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) C.iD[i] = lane_read(addr, Cl.iD[i]);
+  st |= (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)stl);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) fr[a] = ((src >> a) & 1) ? 1.0 : 0.0;
+  if (rm == 0u) boxqp(H, q, lo, hi, xw, piv, x, fr, C, st);
+}
+
 }  // namespace dmpc_dev
