@@ -554,7 +554,13 @@ __device__ void grp_sweep(const KArgs& A, const Grp& G, int n, int kit, double* 
     if (MODE == 0) {
       double kw[4] = {0.0, 0.0, 0.0, 0.0};
       kw[0] = s_kw.x; kw[1] = s_kw.y; kw[2] = s_kw.z; kw[3] = s_kw.w;
-      boxqp_row(H, qu, dl, dh, kw, A.piv, (int)(__lane_id() & 48u), l_s, kv, fr, C, st);
+      // the dense FP64 kernel is at its register limit: the row solver's extra
+      // registers spill inside the stage loop there (13.0 against 9.1 ms
+      // forward at B=16384, T=50), so it keeps the active-set loop
+      if constexpr (DENSE && sizeof(R) == sizeof(double))
+        boxqp(H, qu, dl, dh, kw, A.piv, kv, fr, C, st);
+      else
+        boxqp_row(H, qu, dl, dh, kw, A.piv, (int)(__lane_id() & 48u), l_s, kv, fr, C, st);
     } else {
 #pragma unroll
       for (int a = 0; a < 4; ++a) fr[a] = (zb[NX + a] == G.lo[a] || zb[NX + a] == G.hi[a]) ? 0.0 : 1.0;
