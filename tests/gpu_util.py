@@ -79,7 +79,7 @@ def describe(e):
 
 
 def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=True, grad_u=None, grad_x=None,
-            fp64_pivot=1e-6, ckpt=0, theta=False, tpar=False, f64=False, redo=False):
+            fp64_pivot=1e-6, ckpt=0, theta=False, tpar=False, f64=False, redo=False, tuned=False):
     import torch
 
     import paper_2605_29155_amd as D
@@ -92,6 +92,7 @@ def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=Tru
     flags |= D.TPAR if tpar else 0
     flags |= D.F64 if f64 else 0
     flags |= D.F64_REDO if redo else 0
+    flags |= D.TUNED if tuned else 0
     cfg = D.make_config(B, Tm, d["cost_kind"], K, tol, flags, fp64_pivot, ckpt)
     t = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev) for k in ("x0", "Q", "p", "lo", "hi")}
     Tt = torch.from_numpy(d["T"].astype(np.int32)).to(dev)
@@ -101,6 +102,9 @@ def run_gpu(d, plain=False, lpt=True, need_grad=True, K=None, tol=None, dlog=Tru
     st = torch.zeros(B, dtype=torch.int32, device=dev)
     dl = torch.zeros((B, max(K, 1), 1 + Tm), dtype=torch.uint8, device=dev) if dlog else None
     par = D.quad_params(W.quad_params_f32())
+    if tuned:
+        # the launch choice the autotuner keeps for this shape (as the bench runs it)
+        D.autotune(h, cfg, par, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], Tt, u, x, st, ws)
     D.forward_raw(h, cfg, par, t["x0"], t["Q"], t["p"], t["lo"], t["hi"], Tt, u, x, st, ws, dl)
     out = dict(launches_fwd=h.launch_count())
     if need_grad:

@@ -13,7 +13,7 @@ import oracle as orc
 import workloads as W
 
 from gpu_util import (alpha_choices_valid, decision_agreement, describe, handle, oracle_replay, oracle_sensitivity,
-                      parity_errors, rel, run_gpu, within_bars)
+                      parity_errors, pattern_agreement, rel, run_gpu, within_bars, TOL_G, TOL_U, TOL_VIOL)
 
 pytestmark = pytest.mark.gpu
 
@@ -225,6 +225,45 @@ def test_cfg3_full_size_ragged_all_instances():
           flush=True)
     assert np.mean(flat) >= 0.98
     assert np.all(g32["u"][pad] == 0)
+
+
+def test_cfg2_full_size_all_instances():
+    """The metric workload at full size (B = 4096, T = 20, K = 5, the
+    MLP-emitted cost, the upstream gradient on the first control as in the
+    bench) in the launch configuration the bench times (the autotuner's
+    persistent choice), every instance against the oracle with the kernel's
+    decisions replayed.  FP32 form: u* and the gradients within the flat bars
+    (normwise and element-wise) on every instance, every step length a
+    minimiser of the oracle's candidate costs, a free oracle run taking the
+    kernel's clamp patterns on at least 99% of the instances.  A replayed
+    clamp pattern can fail the oracle's own stage QP where that QP is
+    ill-conditioned and the FP32 form's QP differs from it by FP32 rounding
+    (measured: 1 of the 409,600 stage QPs, relative violation 9e-3, with u*
+    of that instance within 1e-6); at most one in 10^4 may.  FP64 form
+    (DMPC_F64): every instance within every flat bar, every replayed pattern
+    valid."""
+    import paper_2605_29155_amd as D
+    d = W.make(2)
+    g = run_gpu(d, tuned=True)
+    ch = D.last_launch_choice(handle())
+    o = oracle_replay(d, g)
+    e = parity_errors(g, o)
+    agree = pattern_agreement(o)
+    v = o["replay"]["replay_viol"]
+    nbad = int((v > TOL_VIOL).sum())
+    print("cfg2 B=4096 (all), FP32 form, launch %s: %s | stage QPs whose replayed pattern fails the oracle's: %d of %d"
+          " | clamp patterns as a free FP64 run's %.4f" % (ch.as_dict(), describe(e), nbad, v.size, agree), flush=True)
+    assert ch.plain == 0
+    assert np.all((e["u"] <= TOL_U) & (e["u_abs"] <= TOL_U) & (e["g"] <= TOL_G) & (e["g_abs"] <= TOL_G)), describe(e)
+    assert nbad <= 1e-4 * v.size
+    assert alpha_choices_valid(o) == 0
+    assert agree >= 0.99
+    g64 = run_gpu(d, f64=True)
+    o64 = oracle_replay(d, g64, free=False)
+    e64 = parity_errors(g64, o64)
+    print("cfg2 B=4096 (all), FP64 form: %s" % describe(e64), flush=True)
+    assert np.all(within_bars(e64)), describe(e64)
+    assert alpha_choices_valid(o64) == 0
 
 
 def test_long_horizon_parity():
