@@ -236,9 +236,8 @@ def test_cfg2_full_size_all_instances():
     (normwise and element-wise) on every instance, every step length a
     minimiser of the oracle's candidate costs, a free oracle run taking the
     kernel's clamp patterns on at least 99% of the instances.  A replayed
-    clamp pattern can fail the oracle's own stage QP where that QP is
-    ill-conditioned and the FP32 form's QP differs from it by FP32 rounding
-    (measured: 1 of the 409,600 stage QPs, relative violation 9e-3, with u*
+    clamp pattern can fail the oracle's own stage QP where the FP32 form's
+    stage QP differs from it by FP32 rounding (measured: 1 of the 409,600 stage QPs, relative violation 9e-3, with u*
     of that instance within 1e-6); at most one in 10^4 may.  FP64 form
     (DMPC_F64): every instance within every flat bar, every replayed pattern
     valid."""
