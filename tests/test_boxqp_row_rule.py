@@ -30,10 +30,13 @@ def rand_spd(rng, n=4, lo=0.05):
     return M @ M.T + lo * np.eye(n)
 
 
-def face_solve(H, q, lo, hi, free, onlo):
-    """Minimiser on the face: clamped coordinates on their guessed bound,
-    the free ones from the free block's linear system."""
+def face_solve(H, q, lo, hi, free, onlo, xfix=None):
+    """Minimiser on the face: clamped coordinates on their guessed bound (a
+    fixed coordinate, lo >= hi, at xfix), the free ones from the free block's
+    linear system."""
     xc = np.where(onlo, lo, hi)
+    if xfix is not None:
+        xc = np.where(lo >= hi, xfix, xc)
     x = xc.copy()
     f = np.flatnonzero(free)
     if len(f):
@@ -45,17 +48,19 @@ def face_solve(H, q, lo, hi, free, onlo):
 
 def valid(H, q, lo, hi, free, onlo, x):
     g = H @ x + q
+    fixed = ~(lo < hi)
     ok_free = (x >= lo) & (x <= hi)
     ok_clamped = np.where(onlo, g >= 0.0, g <= 0.0)
-    return bool(np.all(np.where(free, ok_free, ok_clamped)))
+    ok = np.where(fixed, ~free, np.where(free, ok_free, ok_clamped))
+    return bool(np.all(ok))
 
 
-def lanes(H, q, lo, hi, onlo):
+def lanes(H, q, lo, hi, onlo, xfix=None):
     """(lane, solution) for every valid lane, lowest first."""
     out = []
     for j in range(16):
         free = np.array([(j >> a) & 1 for a in range(4)], bool)
-        x = face_solve(H, q, lo, hi, free, onlo)
+        x = face_solve(H, q, lo, hi, free, onlo, xfix)
         if valid(H, q, lo, hi, free, onlo, x):
             out.append((j, x))
     return out
@@ -155,3 +160,25 @@ def test_two_guesses_cover_most_stage_qps(orc):
     assert passes[0] <= 0.08 * n
     assert passes[1] >= 0.7 * n
     assert unconstrained_only > passes[0]
+
+
+def test_fixed_coordinates_are_never_free(orc):
+    """A coordinate with lo = hi (a rotor whose thrust is pinned) is held on
+    its bound in every lane and the lanes that would free it are invalid; the
+    valid lane is still the enumeration's minimiser."""
+    rng = np.random.default_rng(7300)
+    seen = 0
+    for _ in range(300):
+        H, q, lo, hi, xw = stage_like(rng)
+        a = rng.integers(0, 4)
+        hi[a] = lo[a]
+        ref, _, st = orc.boxqp(H, q, lo, hi)
+        assert st == 0
+        x0 = np.clip(xw, lo, hi)
+        onlo = first_guess(H, q, lo, hi, xw)
+        for j, x in lanes(H, q, lo, hi, onlo, xfix=x0):
+            assert not (j >> a) & 1
+            assert x[a] == lo[a]
+            assert np.abs(x - ref).max() <= 1e-9 * (1 + np.abs(ref).max())
+            seen += 1
+    assert seen > 150
